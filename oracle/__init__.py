@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the HJ-Gauss Monte-Carlo Picard sweep.
+
+TEST INFRASTRUCTURE.  Plain, slow, obviously correct numpy code written from
+the paper (Algorithm 1; the log-sum-exp, Monte-Carlo gradient and
+tilted-proposal corollaries; the coefficient definition, its regularisation and
+clipping).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it.  It shares no code with the
+device path; the Gaussian draws come from its own Philox4x32-10
+implementation (``oracle.philox``).
+
+Parity status per function (what pins it, see tests/test_oracle_*.py):
+  philox.philox4x32_10 / normals : statistical tests only, plus bit agreement
+                                   with the independent device implementation
+                                   (no published known-answer vectors are
+                                   available here)
+  estimator.value_grad           : closed forms (quadratic H with quadratic and
+                                   linear data), 1D folded-normal closed form,
+                                   2D disk quadrature, c -> 0 limit, tilt
+                                   invariance, Stein vs finite differences,
+                                   N^-1/2 rate
+  estimator.picard               : quadratic-H fixed point in one step,
+                                   deterministic contraction under common
+                                   random numbers; for non-quadratic H the
+                                   Picard fixed point is "parity unpinned"
+                                   against the viscous solution (the paper's
+                                   quasi-linearisation defect is not computable)
+  model.hamiltonian (Dubins)     : brute-force max-min over control grids
+  model.coefficient              : direct evaluation checks (sign, clip, eta)
+"""

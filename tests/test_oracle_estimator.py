@@ -1,0 +1,348 @@
+"""Pins of the oracle's estimators and Picard loop against what the mathematics fixes.
+
+Each check is chosen so that a plausible mistake in the oracle (a dropped
+term, a sign, sigma vs sigma^2, delta vs nu, a transposed operand) fails at
+least one of them:
+
+* closed forms of the exact Cole-Hopf case H = |p|^2/2 (paper, Section 2.1,
+  "Exact case") with quadratic and linear data, evaluated with deterministic
+  equal-probability quantile nodes in place of random draws, so that the
+  comparison is tight instead of statistical;
+* the 1D folded-normal closed form and the 2D Rice-distribution quadrature for
+  signed-distance data;
+* an independent finite-difference solve of v_t + |v_x|^2/2 = nu v_xx
+  (fixes delta = 2 nu);
+* exactness of the tilted estimator with the Laplace shift on linear data
+  (tilted-proposal corollary: ESS = N, value and control-variate gradient exact
+  for every draw);
+* the c -> 0 limit (remark on the sign of the coefficient);
+* Stein gradient vs a finite difference of the value;
+* the N^-1/2 rate of the value error (Section 2.5);
+* brute-force max-min evaluation of the game Hamiltonians.
+"""
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from oracle import estimator, model, philox
+
+
+def quantile_nodes_1d(N1):
+    return special.ndtri((np.arange(N1) + 0.5) / N1)
+
+
+def quantile_grid(n, N1):
+    """[n, N1^n] tensor grid of 1D quantile nodes (equal-weight quadrature)."""
+    q = quantile_nodes_1d(N1)
+    mesh = np.meshgrid(*([q] * n), indexing="ij")
+    return np.stack([m.ravel() for m in mesh])
+
+
+def closed_form_quadratic(x, t, nu):
+    """H = |p|^2/2, l = |x|^2/2: v = |x|^2/(2(1+t)) + n nu log(1+t), Dv = x/(1+t)."""
+    n = x.shape[1]
+    return np.sum(x * x, 1) / (2 * (1 + t)) + n * nu * np.log1p(t), x / (1 + t)
+
+
+# ---------------------------------------------------------------- exact quadratic case
+@pytest.mark.parametrize("tilt_theta", [None, "half", "laplace"])
+def test_quadratic_datum_closed_form_quantile_nodes(tilt_theta):
+    # the equal-probability quantile rule converges like 1/N1 here (weights
+    # peak in the tails when untilted), so N1 = 1500 gives ~1e-4 / ~1e-3.
+    nu, t = 0.05, 0.5
+    pb = model.Problem(n=2, ham="quadratic", datum="half_sqnorm", nu=nu, tilt=True)
+    x = np.array([[0.3, -0.4], [1.0, 0.5], [-0.7, 0.2], [0.0, 0.0]])
+    c = model.coefficient(pb, x, x)
+    assert np.all(c == 1 / (2 * nu))
+    if tilt_theta is None:
+        theta = None
+    elif tilt_theta == "laplace":
+        theta = model.tilt(pb, np.sqrt(pb.delta * t), c, model.datum_grad(pb, x))
+        np.testing.assert_allclose(theta, -t * x)
+    else:                                           # a non-optimal shift
+        theta = -0.5 * t * x
+    z = quantile_grid(2, 1500)
+    est = estimator.value_grad(pb, x, t, z.shape[1], c, theta, z=z)
+    v_ref, g_ref = closed_form_quadratic(x, t, nu)
+    np.testing.assert_allclose(est.v, v_ref, rtol=0, atol=1.5e-4)
+    np.testing.assert_allclose(est.grad, g_ref, rtol=0, atol=2e-3)
+    if tilt_theta == "laplace":                    # near zero-variance proposal
+        np.testing.assert_allclose(est.v, v_ref, rtol=0, atol=2e-5)
+        np.testing.assert_allclose(est.grad, g_ref, rtol=0, atol=2e-4)
+
+
+def test_quadratic_datum_mc_within_standard_error():
+    nu, t, N = 0.05, 0.5, 1 << 15
+    delta = 2 * nu
+    pb = model.Problem(n=2, ham="quadratic", datum="half_sqnorm", nu=nu, seed=11)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1.1, 1.1, size=(64, 2))
+    est = estimator.value_grad(pb, x, t, N, np.full(64, 1 / delta))
+    v_ref, _ = closed_form_quadratic(x, t, nu)
+    # second moment ratio of the weights, per dimension, for this datum
+    ratio = ((1 + t) ** 2 / (1 + 2 * t)) ** 1 * np.exp(np.sum(x * x, 1) * t / (delta * (1 + t) * (1 + 2 * t)))
+    se = delta * np.sqrt((ratio - 1) / N)
+    assert np.all(np.abs(est.v - v_ref) < 5 * se)
+
+
+def test_linear_datum_tilt_is_exact_for_any_draws():
+    nu, t, N = 0.01, 1.0, 4096
+    a = np.array([0.6, -0.8, 0.3])
+    pb = model.Problem(n=3, ham="quadratic", datum="linear", nu=nu, datum_p=(0.25,), datum_aux=a,
+                       tilt=True, grad_cv=True, seed=5)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-2, 2, size=(16, 3))
+    sigma = np.sqrt(pb.delta * t)
+    p = model.datum_grad(pb, x)
+    c = model.coefficient(pb, x, p)
+    theta = model.tilt(pb, sigma, c, p)
+    est = estimator.value_grad(pb, x, t, N, c, theta)
+    v_ref = x @ a + 0.25 - t * np.dot(a, a) / 2
+    np.testing.assert_allclose(est.v, v_ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(est.ess, N, rtol=1e-12)
+    np.testing.assert_allclose(est.grad, np.tile(a, (16, 1)), rtol=0, atol=1e-12)
+    # without the control variate the gradient carries exactly the Stein noise zbar/(c sigma)
+    pb.grad_cv = False
+    est2 = estimator.value_grad(pb, x, t, N, c, theta)
+    np.testing.assert_allclose(est2.grad, a - est2.zbar / (c[:, None] * sigma), rtol=0, atol=1e-12)
+
+
+# The deterministic quantile rule is accurate only where the weights are not
+# concentrated in the tails of z, i.e. for |c| sigma |Dl| = O(1); those pins
+# therefore use nu = 0.25 (c = 2, sigma = 0.5 at t = 0.5).  A mistake in the
+# formulas (delta vs nu, sigma vs sigma^2, a sign) still moves the result by
+# far more than the tolerances.
+def test_linear_datum_untilted_value_matches_hopf_lax():
+    nu, t = 0.25, 0.5
+    a = np.array([1.0, 0.5])
+    pb = model.Problem(n=2, ham="quadratic", datum="linear", nu=nu, datum_p=(-0.5,), datum_aux=a)
+    x = np.array([[0.2, 0.1], [-1.0, 1.0]])
+    z = quantile_grid(2, 2000)
+    est = estimator.value_grad(pb, x, t, z.shape[1], np.full(2, 1 / pb.delta), z=z)
+    np.testing.assert_allclose(est.v, x @ a - 0.5 - t * np.dot(a, a) / 2, atol=7e-4)
+
+
+# ------------------------------------------------------------- signed-distance data
+def folded_normal_value(x, t, nu):
+    """1D, H = p^2/2, l = |x| - 1: v = -(1/c) log E exp(-c(|Y| - 1)), Y ~ N(x, delta t)."""
+    delta = 2 * nu
+    c, s = 1 / delta, np.sqrt(delta * t)
+    mgf = np.exp(c * c * s * s / 2) * (np.exp(-c * x) * special.ndtr(x / s - c * s)
+                                       + np.exp(c * x) * special.ndtr(-x / s - c * s))
+    return -(np.log(mgf) + c) / c
+
+
+def test_1d_abs_datum_closed_form():
+    nu, t = 0.25, 0.5
+    pb = model.Problem(n=1, ham="quadratic", datum="ball", datum_p=(1, 1.0), nu=nu)
+    xs = np.array([-1.5, -0.6, -0.1, 0.0, 0.3, 0.9, 2.0])
+    z = quantile_nodes_1d(1 << 18)[None, :]
+    est = estimator.value_grad(pb, xs[:, None], t, z.shape[1], np.full(len(xs), 1 / pb.delta), z=z)
+    np.testing.assert_allclose(est.v, folded_normal_value(xs, t, nu), atol=2e-5)
+    h = 1e-5
+    dv = (folded_normal_value(xs + h, t, nu) - folded_normal_value(xs - h, t, nu)) / (2 * h)
+    np.testing.assert_allclose(est.grad[:, 0], dv, atol=2e-3)
+
+
+def fd_viscous_1d(nu, t, xs):
+    """Explicit central-difference solve of v_t + v_x^2/2 = nu v_xx, v(0,x) = |x| - 1.
+
+    Independent of the Cole-Hopf transform; domain [-6, 6] with linear
+    extrapolation at the ends (far outside the region checked).
+    """
+    dx = 0.01
+    grid = np.arange(-6, 6 + dx / 2, dx)
+    v = np.abs(grid) - 1.0
+    dt = 0.2 * dx * dx / nu
+    steps = int(np.ceil(t / dt))
+    dt = t / steps
+    for _ in range(steps):
+        vx = (v[2:] - v[:-2]) / (2 * dx)
+        vxx = (v[2:] - 2 * v[1:-1] + v[:-2]) / (dx * dx)
+        v[1:-1] = v[1:-1] + dt * (nu * vxx - 0.5 * vx * vx)
+        v[0] = 2 * v[1] - v[2]
+        v[-1] = 2 * v[-2] - v[-3]
+    return np.interp(xs, grid, v)
+
+
+@pytest.mark.slow
+def test_fd_pde_solve_matches_estimator_1d():
+    nu, t = 0.25, 0.5
+    xs = np.array([-1.2, -0.4, 0.0, 0.25, 0.8, 1.5])
+    pb = model.Problem(n=1, ham="quadratic", datum="ball", datum_p=(1, 1.0), nu=nu)
+    z = quantile_nodes_1d(1 << 18)[None, :]
+    est = estimator.value_grad(pb, xs[:, None], t, z.shape[1], np.full(len(xs), 1 / pb.delta), z=z)
+    np.testing.assert_allclose(est.v, fd_viscous_1d(nu, t, xs), atol=2e-4)
+
+
+def rice_value(r0, t, nu, R=1.0):
+    """2D, H = |p|^2/2, l = |x| - R: E exp(-c(|Y| - R)) with |Y| ~ Rice(r0, sigma)."""
+    delta = 2 * nu
+    c, s = 1 / delta, np.sqrt(delta * t)
+    dist = stats.rice(r0 / s, scale=s)
+    lo, hi = max(0.0, r0 - 12 * s), r0 + 12 * s
+    val, _ = integrate.quad(lambda r: np.exp(-c * (r - R)) * dist.pdf(r), lo, hi, epsabs=0, epsrel=1e-12, limit=400)
+    return -np.log(val) / c
+
+
+def test_2d_disk_datum_rice_quadrature():
+    nu, t = 0.25, 0.5
+    pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=nu)
+    x = np.array([[1.2, 0.3], [0.2, -0.5], [0.0, 1.0], [-1.4, -0.9]])
+    z = quantile_grid(2, 1000)
+    est = estimator.value_grad(pb, x, t, z.shape[1], np.full(len(x), 1 / pb.delta), z=z)
+    r0 = np.linalg.norm(x, axis=1)
+    v_ref = np.array([rice_value(r, t, nu) for r in r0])
+    np.testing.assert_allclose(est.v, v_ref, atol=3e-4)
+    h = 1e-4
+    dvdr = np.array([(rice_value(r + h, t, nu) - rice_value(r - h, t, nu)) / (2 * h) for r in r0])
+    np.testing.assert_allclose(est.grad, (dvdr / r0)[:, None] * x, atol=3e-3)
+
+
+# ----------------------------------------------------------------- limits and invariants
+def test_c_to_zero_limit_is_gaussian_mean():
+    pb = model.Problem(n=3, ham="zero", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
+                       c_min=1e-9, seed=2)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-2, 2, size=(8, 3))
+    c = model.coefficient(pb, x, model.datum_grad(pb, x))
+    assert np.all(c == 1e-9)
+    N, t = 2048, 1.0
+    est = estimator.value_grad(pb, x, t, N, c)
+    z = philox.crn_table(pb.seed, 0, 0, 3, N)
+    y = x[:, None, :] + np.sqrt(pb.delta * t) * z.T[None]
+    mean_l = np.mean(model.datum(pb, y), axis=1)
+    np.testing.assert_allclose(est.v, mean_l, atol=1e-7)
+
+
+def test_stein_gradient_matches_fd_of_value():
+    nu, t = 0.25, 0.5
+    pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=nu)
+    x = np.array([[1.2, 0.3], [0.4, -0.9]])
+    z = quantile_grid(2, 900)
+    c = np.full(2, 1 / pb.delta)
+    est = estimator.value_grad(pb, x, t, z.shape[1], c, z=z)
+    h = 1e-3
+    fd = np.zeros_like(x)
+    for d in range(2):
+        e = np.zeros(2)
+        e[d] = h
+        fd[:, d] = (estimator.value_grad(pb, x + e, t, z.shape[1], c, z=z).v
+                    - estimator.value_grad(pb, x - e, t, z.shape[1], c, z=z).v) / (2 * h)
+    np.testing.assert_allclose(est.grad, fd, atol=3e-3)
+
+
+@pytest.mark.slow
+def test_value_error_decays_as_inverse_sqrt_n():
+    nu, t = 0.05, 0.5
+    x = np.array([[0.5, -0.3], [0.2, 0.8]])
+    v_ref, _ = closed_form_quadratic(x, t, nu)
+    Ns = [1 << k for k in range(8, 15)]
+    rms = []
+    for N in Ns:
+        errs = []
+        for seed in range(30):
+            pb = model.Problem(n=2, ham="quadratic", datum="half_sqnorm", nu=nu, seed=1000 + seed)
+            est = estimator.value_grad(pb, x, t, N, np.full(2, 1 / pb.delta))
+            errs.append(est.v - v_ref)
+        rms.append(np.sqrt(np.mean(np.square(errs))))
+    slope = np.polyfit(np.log(Ns), np.log(rms), 1)[0]
+    assert -0.6 < slope < -0.4
+
+
+def test_tilt_consistency_many_seeds():
+    # every shift gives a consistent estimator (tilted-proposal corollary)
+    nu, t, N = 0.05, 0.5, 4096
+    x = np.array([[0.6, -0.2]])
+    v_ref, _ = closed_form_quadratic(x, t, nu)
+    for th in ([0.0, 0.0], [0.15, -0.05], [-0.3, 0.1]):
+        vs = []
+        for seed in range(40):
+            pb = model.Problem(n=2, ham="quadratic", datum="half_sqnorm", nu=nu, seed=seed + 77)
+            vs.append(estimator.value_grad(pb, x, t, N, np.full(1, 1 / pb.delta), np.array([th])).v[0])
+        vs = np.array(vs)
+        assert abs(vs.mean() - v_ref[0]) < 5 * vs.std() / np.sqrt(len(vs)) + 1e-4
+
+
+# ------------------------------------------------------------------- Hamiltonians
+def brute_dubins(x, p, s_sign=1.0):
+    """max over the evader turn rate, min over the pursuer's, from the relative dynamics."""
+    ctrl = np.linspace(-1, 1, 201)
+    H = 0.0
+    for j in range(len(x) // 3):
+        x1, x2, x3 = x[3 * j:3 * j + 3]
+        p1, p2, p3 = p[3 * j:3 * j + 3]
+        best = -np.inf
+        for we in ctrl:
+            worst = np.inf
+            for wp in ctrl:
+                f = np.array([-1 + np.cos(x3) + we * x2, s_sign * np.sin(x3) - we * x1, wp - we])
+                worst = min(worst, p1 * f[0] + p2 * f[1] + p3 * f[2])
+            best = max(best, worst)
+        H += best
+    return H
+
+
+def test_dubins_hamiltonian_brute_force():
+    rng = np.random.default_rng(9)
+    pb = model.Problem(n=6, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01)
+    for _ in range(5):
+        x = rng.uniform(-3, 3, 6)
+        p = rng.standard_normal(6)
+        H = model.hamiltonian(pb, x[None], p[None])[0]
+        assert abs(H - brute_dubins(x, p)) < 1e-9
+    # the printed variant flips the sign of the p2 sin(x3) term
+    pb.ham_p = (-1.0, 1.0, 1.0, 1.0)
+    x, p = rng.uniform(-3, 3, 6), rng.standard_normal(6)
+    assert abs(model.hamiltonian(pb, x[None], p[None])[0] - brute_dubins(x, p, -1.0)) < 1e-9
+
+
+def test_double_integrator_hamiltonian_brute_force():
+    rng = np.random.default_rng(10)
+    pb = model.Problem(n=6, ham="double_integrator", datum="knn_balls", nu=0.02, ham_p=(1.0,))
+    dirs = rng.standard_normal((200000, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    x, p = rng.standard_normal(6), rng.standard_normal(6)
+    brute = p[:3] @ x[3:] + np.max(dirs @ p[3:])
+    assert abs(model.hamiltonian(pb, x[None], p[None])[0] - brute) < 1e-3
+
+
+def test_coefficient_sign_clip_and_regularisation():
+    pb = model.Problem(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
+                       eta=0.01, c_min=0.5, c_max=20.0)
+    x = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.3], [2.0, 2.0, 2.0]])
+    p = np.array([[0.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.3, -0.2, 0.1]])
+    H = model.hamiltonian(pb, x, p)
+    raw = (2 / pb.delta) * H / (np.sum(p * p, 1) + pb.eta)
+    c = model.coefficient(pb, x, p)
+    assert c[0] == 0.5                                  # H = 0 -> +c_min
+    for ci, ri in zip(c[1:], raw[1:]):
+        assert np.sign(ci) == np.sign(ri) and 0.5 <= abs(ci) <= 20.0
+
+
+# ---------------------------------------------------------------- Picard loop
+def test_picard_quadratic_is_fixed_after_one_step_crn():
+    pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=0.05, seed=3)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-2, 2, (32, 2))
+    res = estimator.picard(pb, x, 0.5, 2048, K=3)
+    assert res.iters_done == 3
+    assert res.resid_hist[1] == 0.0 and res.resid_hist[2] == 0.0
+
+
+def test_picard_linear_datum_exact_each_iteration_with_tilt():
+    a = np.array([0.3, 0.4, -0.5])
+    pb = model.Problem(n=3, ham="quadratic", datum="linear", nu=0.01, datum_p=(0.1,), datum_aux=a,
+                       tilt=True, grad_cv=True, seed=8)
+    x = np.random.default_rng(6).uniform(-3, 3, (10, 3))
+    res = estimator.picard(pb, x, 1.0, 1024, K=4)
+    np.testing.assert_allclose(res.v, x @ a + 0.1 - np.dot(a, a) / 2, atol=1e-12)
+    np.testing.assert_allclose(res.grad, np.tile(a, (10, 1)), atol=1e-12)
+
+
+def test_picard_early_exit_and_flags():
+    pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=0.05, seed=3)
+    x = np.random.default_rng(5).uniform(-2, 2, (32, 2))
+    res = estimator.picard(pb, x, 0.5, 2048, K=5, tol=1e-6)
+    assert res.iters_done == 2 and res.resid_hist[-1] == 0.0
+    assert not res.flags.any()
