@@ -1,0 +1,207 @@
+/*
+ * hjg.h -- C interface of the HJ-Gauss Monte-Carlo Picard sweep on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library solves the viscous Hamilton-Jacobi(-Isaacs) problem
+ *     v_t + H(x, Dv) = nu * Lap v,   v(0, x) = l(x)        (t = time-to-go)
+ * pointwise at batches of evaluation states, by the frozen-coefficient
+ * (Picard) quasi-linearisation of Algorithm 1 of the HJ-Gauss paper
+ * (Molu, Renganathan, Cho).  In the paper's notation delta = 2 nu and the
+ * heat kernel of one step is N(x, delta t I).  One step, for each state x with
+ * frozen coefficient c and proposal shift theta, draws z_i ~ N(0, I_n) and
+ * forms (log-sum-exp, Monte-Carlo gradient and tilted-proposal corollaries of
+ * the appendix; ESS as in Section 2.4):
+ *     y_i = x + theta + sigma z_i,        sigma^2 = delta t
+ *     a_i = -c l(y_i) - |theta|^2/(2 sigma^2) - <z_i, theta>/sigma
+ *     v   = -(1/c) log((1/N) sum_i e^{a_i})
+ *     Dv  = -(theta + sigma (sum_i e^{a_i} z_i / sum_i e^{a_i} - [zbar])) / (c sigma^2)
+ *     ESS = (sum_i e^{a_i})^2 / sum_i e^{2 a_i}
+ * where [zbar] = (1/N) sum_i z_i is subtracted only with grad_cv (a control
+ * variate with mean zero).  The coefficient is c = (2/delta) H / (|p|^2 + eta)
+ * with |c| clipped to [c_min, c_max] and its sign kept, sign(0) = +1
+ * (coefficient definition of Section 2.1, the regularised-coefficient lemma
+ * and the remark on the coefficient's sign); for H = |p|^2/2 it is exactly
+ * 1/delta.  The Laplace shift is theta = -sigma^2 c p (Section 2.4).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays marked "device" are device pointers on the context's GPU, owned by
+ *    the caller; "host" arrays are host memory owned by the caller.  The
+ *    library owns only the context (workspace, sample-table cache, graphs).
+ *  - State arrays are dimension-major ("SoA"): element (d, q) of an [n][Q]
+ *    array sits at index d*Q + q.  All floating-point arrays are float32
+ *    unless stated otherwise.
+ *  - Calls are asynchronous on the HIP stream passed in (NULL = default
+ *    stream), except those with host outputs, which synchronise that stream
+ *    before returning.
+ *  - Arguments are validated before anything is launched; on error nothing is
+ *    written, the return value is negative and hjg_last_error() describes it.
+ *  - The Gaussian draws are Philox4x32-10 (Salmon et al., SC'11) with the
+ *    stream layout documented at hjg_philox4x32_10 below; they are
+ *    reproducible bit for bit from (seed, problem_id, time_step, iteration,
+ *    query).
+ *  - Not thread-safe per context: calls that share an hjg_ctx must be
+ *    serialised by the caller.
+ */
+#ifndef HJG_H
+#define HJG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum hjg_status {
+  HJG_OK = 0,
+  HJG_ENOTCONVERGED = 1,  /* warning: outputs valid, tolerance not reached  */
+  HJG_EINVAL = -1,        /* invalid argument, nothing launched              */
+  HJG_ENOMEM = -2,        /* device workspace allocation failed              */
+  HJG_EHIP = -3,          /* HIP runtime error                               */
+  HJG_ENONFINITE = -4,    /* a non-finite value appeared in an output        */
+  HJG_EUNSUPPORTED = -5   /* valid but unsupported combination               */
+};
+
+/* Hamiltonians H(x, p) = max_u min_w <p, f(x, u, w)>. */
+enum hjg_ham {
+  HJG_H_QUADRATIC = 0,       /* |p|^2/2; c = 1/delta exactly                           */
+  HJG_H_DUBINS_PAIRS = 1,    /* sum over stacked relative Dubins pairs (n = 3m):
+                                p1 (v_p cos x3 - v_e) + s p2 v_p sin x3
+                                + w |p1 x2 - p2 x1 - p3| - w |p3|;
+                                ham_p = {s, v_e, v_p, w}.  s = +1 follows from the
+                                relative dynamics of the Dubins game in the
+                                appendix, s = -1 is the form printed there.      */
+  HJG_H_ZERO = 2,            /* H = 0 (pure diffusion; c = +c_min)                     */
+  HJG_H_DOUBLE_INTEGRATOR = 3/* n = 6, x = (pos, vel): <p_pos, vel> + u_max |p_vel|;
+                                ham_p = {u_max}                                       */
+};
+
+/* Terminal data l(y) (signed distance: negative inside the target set). */
+enum hjg_datum {
+  HJG_L_HALF_SQNORM = 0,     /* |y|^2 / 2                                              */
+  HJG_L_BALL = 1,            /* |y[0:k]| - r; datum_p = {k, r}                         */
+  HJG_L_MIN_PAIR_DISKS = 2,  /* min_j |(y[3j], y[3j+1])| - r (union of discs, n = 3m);
+                                datum_p = {r}                                         */
+  HJG_L_KNN_BALLS = 3,       /* min_j |y[0:3] - nb_j(q)| - r over the query's K
+                                neighbour positions; datum_p = {r, K}, K <= 8;
+                                datum_aux = device [K][3][Q]                          */
+  HJG_L_LINEAR = 4           /* <a, y> + b; datum_p = {b}; datum_aux = device a[n]     */
+};
+
+/* Where the draws come from. */
+enum hjg_sample_mode {
+  HJG_S_FRESH = 0,      /* fresh draws per (query, iteration), generated in registers
+                           (the paper's setting); n <= 16                           */
+  HJG_S_CRN_STEP = 1    /* one common table z[n][N] per (problem, time step), shared
+                           by every query and every Picard iteration               */
+};
+
+typedef struct hjg_problem {
+  int32_t n;               /* state dimension, 1..48                               */
+  int32_t ham;             /* enum hjg_ham                                          */
+  double ham_p[4];
+  int32_t datum;           /* enum hjg_datum                                        */
+  double datum_p[4];
+  const float* datum_aux;  /* device; see hjg_datum, else NULL                      */
+  double nu;               /* viscosity; delta = 2 nu; > 0                          */
+  double eta;              /* coefficient regulariser (>= 0)                        */
+  double c_min, c_max;     /* clip range of |c| (0 < c_min <= c_max)                */
+  int32_t tilt;            /* 1: Laplace shift theta = -sigma^2 c p from the current
+                              gradient iterate (Section 2.4); 0: theta = 0          */
+  int32_t sample_mode;     /* enum hjg_sample_mode                                  */
+  int32_t sample_bf16;     /* 1: draws rounded to bfloat16 (nearest, ties to even)
+                              and stored as bfloat16; arithmetic stays float32     */
+  int32_t grad_cv;         /* 1: subtract zbar in the gradient (control variate)    */
+  uint64_t seed;           /* Philox key                                            */
+  uint32_t problem_id;     /* < 65536; part of the Philox tag                       */
+} hjg_problem;
+
+typedef struct hjg_ctx hjg_ctx;
+
+/* Create a context on HIP device `device`.  Returns HJG_OK and *out, or an
+ * error (HJG_EHIP if the device cannot be used). */
+int hjg_ctx_create(int device, hjg_ctx** out);
+/* Release a context and all its device memory.  NULL is a no-op. */
+void hjg_ctx_destroy(hjg_ctx* ctx);
+/* Description of the last error on the calling thread ("" if none).  Valid
+ * until the next call on that thread. */
+const char* hjg_last_error(void);
+/* Library version string. */
+const char* hjg_version(void);
+
+/*
+ * Raw Philox4x32-10 words: for g in [0, G), out[4g + j] is word j of the block
+ * cipher applied to counter (g, c1, c2, c3) under key (seed mod 2^32,
+ * seed div 2^32).  The library's draws use counter
+ * (i div 4, d, stream, tag) for sample i in dimension d, stream = query index
+ * (FRESH) or 0xFFFFFFFF (common tables), tag = problem_id<<16 | time_step<<8 |
+ * iteration, and map the words (w0, w1, w2, w3) to the normals of samples
+ * 4g .. 4g+3 by Box-Muller on (w0, w1) and (w2, w3):
+ *   u_a = ((w >> 8) + 1) 2^-24, u_b = (w >> 8) 2^-24,
+ *   (r cos 2 pi u_b, r sin 2 pi u_b), r = sqrt(-2 ln u_a).
+ * out: device uint32[4G].  Exposed so the draws can be checked bit for bit.
+ */
+int hjg_philox4x32_10(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t G, uint32_t* out, void* hip_stream);
+
+/*
+ * The common-random-number table of (problem, time_step): z[d][i] for d < n,
+ * i < N, written to out (device, [n][N]); float32, or bfloat16 bits (uint16)
+ * when problem->sample_bf16.  Used internally by the CRN mode; exposed for
+ * checking.
+ */
+int hjg_sample_table(hjg_ctx* ctx, const hjg_problem* problem, int32_t N,
+                     uint32_t time_step, void* out, void* hip_stream);
+
+/*
+ * One frozen-coefficient sweep (the estimators above) at Q states.
+ *   x      device [n][Q]   evaluation states
+ *   t      horizon (> 0)
+ *   N      samples per state (>= 1)
+ *   time_step, iter        Philox tag fields (iter used in FRESH mode only)
+ *   c      device [Q]      frozen coefficient per state (non-zero, finite)
+ *   theta  device [n][Q]   proposal shift, or NULL for theta = 0
+ *   v      device [Q]      out: value
+ *   grad   device [n][Q]   out: gradient
+ *   ess    device [Q]      out: effective sample size, or NULL
+ * Q = 0 is a no-op.  Returns HJG_ENONFINITE if an output is not finite
+ * (checked only when check_finite != 0; the check synchronises the stream).
+ */
+int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
+                   const float* x, double t, int32_t N, uint32_t time_step,
+                   uint32_t iter, const float* c, const float* theta,
+                   float* v, float* grad, float* ess, int32_t check_finite,
+                   void* hip_stream);
+
+/*
+ * Algorithm 1 at Q states and horizon t: v^(0) = l(x), p^(0) = D l(x) (or p0),
+ * then for k = 0..K-1: c^(k) = coefficient(x, p^(k)), theta^(k) (if tilt),
+ * one sweep -> v^(k+1), Dv^(k+1); p^(k+1) = Dv^(k+1).  Stops after iteration k
+ * when the relative L2 change ||v^(k+1) - v^(k)|| / ||v^(k)|| over the Q states
+ * (float64) is below tol (tol <= 0: run all K).  The K iterations are recorded
+ * once into a HIP graph and replayed; the stop is a device-side flag.
+ *   p0        device [n][Q] warm-start gradient, or NULL for D l(x)
+ *   v, grad   device out, [Q] and [n][Q]: the last executed iterate
+ *   c_out     device [Q] out: coefficient frozen in the last executed iteration,
+ *             or NULL
+ *   ess       device [Q] out, or NULL
+ *   flags     device uint8 [Q] out: per-state relative change
+ *             |dv| / max(|v^(k)|, 1e-2 sigma sqrt(n)) > tol at the last
+ *             executed iteration, or NULL
+ *   resid_hist host double [K] out: relative change per iteration (entries
+ *             after the stop are set to 0), or NULL
+ *   iters_done host out: number of executed iterations, or NULL
+ * Synchronises the stream when resid_hist or iters_done is given or tol > 0.
+ * Returns HJG_ENOTCONVERGED (outputs valid) when tol > 0 was not reached.
+ */
+int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
+                     const float* x, double t, int32_t N, int32_t K, double tol,
+                     uint32_t time_step, const float* p0, float* v, float* grad,
+                     float* c_out, float* ess, uint8_t* flags,
+                     double* resid_hist, int32_t* iters_done, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJG_H */

@@ -1,0 +1,9 @@
+"""HJ-Gauss Monte-Carlo Picard sweep on AMD Instinct MI355X (gfx950).
+
+The work runs in libhjg.so (HIP kernels behind the C interface of
+include/hjg.h); this package is its thin Python binding.
+"""
+from .api import (Context, PicardOut, ProblemSpec, philox_words, picard_sweep, sample_table,  # noqa: F401
+                  value_grad)
+
+__all__ = ["Context", "ProblemSpec", "PicardOut", "philox_words", "sample_table", "value_grad", "picard_sweep"]

@@ -1,0 +1,191 @@
+"""Python binding of the HIP library: argument marshalling only.
+
+Every step of the sweep runs in the library's kernels; torch provides device
+memory and the stream.  Arrays are dimension-major ([n][Q]) float32 CUDA
+tensors, as in include/hjg.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+@dataclass
+class ProblemSpec:
+    """Python view of struct hjg_problem (see include/hjg.h for each field)."""
+    n: int
+    ham: str = "quadratic"
+    datum: str = "ball"
+    nu: float = 0.05
+    ham_p: Sequence[float] = (1.0, 1.0, 1.0, 1.0)
+    datum_p: Sequence[float] = ()
+    datum_aux: Optional[torch.Tensor] = None
+    eta: float = 1e-2
+    c_min: float = 1e-2
+    c_max: float = 1e4
+    tilt: bool = False
+    sample_mode: str = "crn_step"
+    sample_bf16: bool = False
+    grad_cv: bool = False
+    seed: int = 0
+    problem_id: int = 0
+
+    def to_c(self) -> _lib.Problem:
+        p = _lib.Problem()
+        p.n = self.n
+        p.ham = _lib.HAMILTONIANS[self.ham]
+        p.datum = _lib.DATUMS[self.datum]
+        hp = list(self.ham_p) + [0.0] * (4 - len(self.ham_p))
+        dp = list(self.datum_p) + [0.0] * (4 - len(self.datum_p))
+        for i in range(4):
+            p.ham_p[i] = float(hp[i])
+            p.datum_p[i] = float(dp[i])
+        if self.datum_aux is not None:
+            _require_cuda(self.datum_aux, "datum_aux")
+            p.datum_aux = self.datum_aux.data_ptr()
+        else:
+            p.datum_aux = None
+        p.nu, p.eta, p.c_min, p.c_max = float(self.nu), float(self.eta), float(self.c_min), float(self.c_max)
+        p.tilt = int(bool(self.tilt))
+        p.sample_mode = _lib.SAMPLE_MODES[self.sample_mode]
+        p.sample_bf16 = int(bool(self.sample_bf16))
+        p.grad_cv = int(bool(self.grad_cv))
+        p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        p.problem_id = int(self.problem_id)
+        return p
+
+
+def _require_cuda(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream or None
+
+
+class Context:
+    """An hjg_ctx on one device (workspace, draw-table cache, recorded graphs)."""
+
+    def __init__(self, device: int = 0):
+        L = _lib.lib()
+        h = C.c_void_p()
+        check(L.hjg_ctx_create(int(device), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().hjg_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def philox_words(seed: int, c1: int, c2: int, c3: int, G: int, device="cuda", stream=None) -> np.ndarray:
+    """Raw Philox4x32-10 words for counters (g, c1, c2, c3), g < G, as uint32 [G, 4]."""
+    out = torch.empty(4 * G, dtype=torch.int32, device=device)
+    check(_lib.lib().hjg_philox4x32_10(int(seed) & (2 ** 64 - 1), c1, c2, c3, G, _ptr(out), _stream(stream)))
+    return out.cpu().numpy().view(np.uint32).reshape(G, 4)
+
+
+def sample_table(ctx: Context, spec: ProblemSpec, N: int, time_step: int = 0, stream=None) -> torch.Tensor:
+    """The common draw table z[n][N]: float32, or bfloat16 when spec.sample_bf16."""
+    dtype = torch.bfloat16 if spec.sample_bf16 else torch.float32
+    out = torch.empty((spec.n, N), dtype=dtype, device=f"cuda:{ctx.device}")
+    p = spec.to_c()
+    check(_lib.lib().hjg_sample_table(ctx.handle, C.byref(p), int(N), int(time_step), _ptr(out), _stream(stream)))
+    return out
+
+
+def value_grad(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, c: torch.Tensor,
+               theta: Optional[torch.Tensor] = None, time_step: int = 0, iteration: int = 0,
+               check_finite: bool = False, out=None, stream=None):
+    """One frozen-coefficient sweep; returns (v [Q], grad [n][Q], ess [Q])."""
+    _require_cuda(x, "x")
+    n, Q = x.shape
+    if n != spec.n:
+        raise ValueError("x must have shape [n, Q]")
+    _require_cuda(c, "c")
+    if theta is not None:
+        _require_cuda(theta, "theta")
+    if out is None:
+        v = torch.empty(Q, dtype=torch.float32, device=x.device)
+        grad = torch.empty((n, Q), dtype=torch.float32, device=x.device)
+        ess = torch.empty(Q, dtype=torch.float32, device=x.device)
+    else:
+        v, grad, ess = out
+    p = spec.to_c()
+    check(_lib.lib().hjg_value_grad(ctx.handle, C.byref(p), Q, _ptr(x), float(t), int(N), int(time_step),
+                                    int(iteration), _ptr(c), _ptr(theta), _ptr(v), _ptr(grad), _ptr(ess),
+                                    int(bool(check_finite)), _stream(stream)))
+    return v, grad, ess
+
+
+@dataclass
+class PicardOut:
+    v: torch.Tensor
+    grad: torch.Tensor
+    c: torch.Tensor
+    ess: torch.Tensor
+    flags: torch.Tensor
+    resid_hist: np.ndarray
+    iters_done: int
+    status: int
+
+
+def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, K: int, tol: float = 0.0,
+                 time_step: int = 0, p0: Optional[torch.Tensor] = None, host_outputs: bool = True,
+                 out: Optional[PicardOut] = None, stream=None) -> PicardOut:
+    """Algorithm 1 at the states x [n][Q]; see hjg_picard_sweep."""
+    _require_cuda(x, "x")
+    n, Q = x.shape
+    if n != spec.n:
+        raise ValueError("x must have shape [n, Q]")
+    if p0 is not None:
+        _require_cuda(p0, "p0")
+    dev = x.device
+    if out is None:
+        out = PicardOut(torch.empty(Q, dtype=torch.float32, device=dev),
+                        torch.empty((n, Q), dtype=torch.float32, device=dev),
+                        torch.empty(Q, dtype=torch.float32, device=dev),
+                        torch.empty(Q, dtype=torch.float32, device=dev),
+                        torch.empty(Q, dtype=torch.uint8, device=dev),
+                        np.zeros(K), 0, 0)
+    hist = (C.c_double * K)() if host_outputs else None
+    iters = C.c_int32(0)
+    p = spec.to_c()
+    code = _lib.lib().hjg_picard_sweep(ctx.handle, C.byref(p), Q, _ptr(x), float(t), int(N), int(K), float(tol),
+                                       int(time_step), _ptr(p0), _ptr(out.v), _ptr(out.grad), _ptr(out.c),
+                                       _ptr(out.ess), _ptr(out.flags), hist,
+                                       C.byref(iters) if host_outputs else None, _stream(stream))
+    check(code, allow=(_lib.HJG_OK, _lib.HJG_ENOTCONVERGED))
+    out.status = code
+    if host_outputs:
+        out.resid_hist = np.array(list(hist))
+        out.iters_done = int(iters.value)
+    return out

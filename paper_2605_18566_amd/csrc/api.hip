@@ -1,0 +1,628 @@
+// Host runtime and C interface: context, workspace, argument checks,
+// common-table cache, launch planning and the graph-recorded Picard loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hjg.h"
+#include "kernels.h"
+
+using namespace hjg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HJG_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(HJG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+struct hjg_ctx {
+  int device = 0;
+  hipStream_t cap = nullptr;   // stream used only to record graphs
+  // workspace
+  DevBuf pm, pS, pS2, pG, pZ, vprev, cwork, thwork, blockpart, resid, ctrl, table, zbar;
+  // common-table cache
+  bool table_valid = false;
+  uint64_t t_seed = 0;
+  uint32_t t_pid = 0, t_step = 0;
+  int t_n = 0, t_N = 0, t_bf16 = 0;
+  int64_t t_stride = 0;
+  int zbar_valid = 0;
+  // recorded Picard graphs
+  struct Graph {
+    std::vector<char> key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+};
+
+namespace {
+
+void drop_graphs(hjg_ctx* ctx) {
+  for (auto& g : ctx->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  ctx->graphs.clear();
+}
+
+// Grow a workspace buffer; any growth invalidates recorded graphs (they hold
+// raw addresses) and waits for the device first so no kernel still uses it.
+int ensure(hjg_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes) return HJG_OK;
+  HJG_HIP(hipDeviceSynchronize());
+  drop_graphs(ctx);
+  if (b.p) HJG_HIP(hipFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  const size_t want = std::max<size_t>(bytes, 256);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(HJG_ENOMEM, "device workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  b.bytes = want;
+  if (&b == &ctx->table) ctx->table_valid = false;
+  return HJG_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+int check_problem(const hjg_problem* p) {
+  if (!p) return fail(HJG_EINVAL, "problem is NULL");
+  if (p->n < 1 || p->n > kMaxN) return fail(HJG_EINVAL, "n must be in [1, 48]");
+  if (!finite_pos(p->nu)) return fail(HJG_EINVAL, "nu must be finite and > 0");
+  if (!(std::isfinite(p->eta) && p->eta >= 0)) return fail(HJG_EINVAL, "eta must be finite and >= 0");
+  if (!finite_pos(p->c_min) || !finite_pos(p->c_max) || p->c_min > p->c_max)
+    return fail(HJG_EINVAL, "need 0 < c_min <= c_max, both finite");
+  if (p->problem_id >= (1u << 16)) return fail(HJG_EINVAL, "problem_id must be < 65536");
+  if (p->sample_mode != HJG_S_FRESH && p->sample_mode != HJG_S_CRN_STEP)
+    return fail(HJG_EINVAL, "unknown sample_mode");
+  if (p->sample_mode == HJG_S_FRESH && p->n > 16)
+    return fail(HJG_EUNSUPPORTED, "fresh draws are supported for n <= 16; use a common table");
+  switch (p->ham) {
+    case HJG_H_QUADRATIC:
+    case HJG_H_ZERO:
+      break;
+    case HJG_H_DUBINS_PAIRS:
+      if (p->n % 3) return fail(HJG_EINVAL, "Dubins pairs need n = 3m");
+      for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
+      break;
+    case HJG_H_DOUBLE_INTEGRATOR:
+      if (p->n != 6) return fail(HJG_EINVAL, "the double integrator needs n = 6");
+      if (!(std::isfinite(p->ham_p[0]) && p->ham_p[0] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
+      break;
+    default:
+      return fail(HJG_EINVAL, "unknown Hamiltonian");
+  }
+  switch (p->datum) {
+    case HJG_L_HALF_SQNORM:
+      break;
+    case HJG_L_BALL: {
+      const double k = p->datum_p[0];
+      if (!(k >= 1 && k <= p->n && k == std::floor(k))) return fail(HJG_EINVAL, "ball: datum_p[0] = k in [1, n]");
+      if (!std::isfinite(p->datum_p[1])) return fail(HJG_EINVAL, "ball: radius must be finite");
+      break;
+    }
+    case HJG_L_MIN_PAIR_DISKS:
+      if (p->n % 3) return fail(HJG_EINVAL, "min_pair_disks needs n = 3m");
+      if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
+      break;
+    case HJG_L_KNN_BALLS: {
+      const double k = p->datum_p[1];
+      if (p->n != 6) return fail(HJG_EINVAL, "knn_balls needs n = 6 (position, velocity)");
+      if (!(k >= 1 && k <= kMaxKnn && k == std::floor(k))) return fail(HJG_EINVAL, "knn_balls: K in [1, 8]");
+      if (!p->datum_aux) return fail(HJG_EINVAL, "knn_balls needs datum_aux");
+      if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
+      break;
+    }
+    case HJG_L_LINEAR:
+      if (!p->datum_aux) return fail(HJG_EINVAL, "linear datum needs datum_aux = a[n]");
+      if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "offset must be finite");
+      break;
+    default:
+      return fail(HJG_EINVAL, "unknown datum");
+  }
+  return HJG_OK;
+}
+
+DatumP datum_params(const hjg_problem* p) {
+  DatumP d;
+  d.kind = p->datum;
+  d.n = p->n;
+  d.k = 0;
+  d.m = p->n / 3;
+  d.r = 0.f;
+  d.aux = p->datum_aux;
+  switch (p->datum) {
+    case HJG_L_BALL: d.k = (int)p->datum_p[0]; d.r = (float)p->datum_p[1]; break;
+    case HJG_L_MIN_PAIR_DISKS: d.r = (float)p->datum_p[0]; break;
+    case HJG_L_KNN_BALLS: d.r = (float)p->datum_p[0]; d.k = (int)p->datum_p[1]; break;
+    case HJG_L_LINEAR: d.r = (float)p->datum_p[0]; break;
+    default: break;
+  }
+  return d;
+}
+
+HamP ham_params(const hjg_problem* p) {
+  HamP h;
+  h.kind = p->ham;
+  h.n = p->n;
+  for (int i = 0; i < 4; ++i) h.p[i] = (float)p->ham_p[i];
+  const double delta = 2.0 * p->nu;
+  h.inv_delta = (float)(1.0 / delta);
+  h.two_over_delta = (float)(2.0 / delta);
+  h.eta = (float)p->eta;
+  h.c_min = (float)p->c_min;
+  h.c_max = (float)p->c_max;
+  return h;
+}
+
+uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter) { return (pid << 16) | (step << 8) | iter; }
+
+struct Plan {
+  int splits;
+  int ns;
+};
+
+// Cut the N samples of each query into contiguous splits so that the launch
+// has enough blocks to fill 256 CUs (about 8 resident blocks each).
+Plan plan_splits(int64_t Q, int N, bool fresh) {
+  int target = 2048;
+  if (const char* e = std::getenv("HJG_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
+  const int64_t qblocks = div_up(Q, kThreads);
+  const int gran = fresh ? 64 : kBlk;
+  int64_t splits = std::max<int64_t>(1, div_up(target, qblocks));
+  splits = std::min<int64_t>(splits, div_up(N, gran));
+  int64_t ns = div_up(div_up(N, splits), gran) * gran;
+  splits = div_up(N, ns);
+  return Plan{(int)splits, (int)ns};
+}
+
+int ensure_partials(hjg_ctx* ctx, int n, int64_t Q, const Plan& pl, bool with_z) {
+  const size_t sq = (size_t)pl.splits * (size_t)Q;
+  int rc;
+  if ((rc = ensure(ctx, ctx->pm, sq * sizeof(float)))) return rc;
+  if ((rc = ensure(ctx, ctx->pS, sq * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->pS2, sq * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->pG, sq * n * sizeof(float)))) return rc;
+  if (with_z && (rc = ensure(ctx, ctx->pZ, sq * n * sizeof(float)))) return rc;
+  return HJG_OK;
+}
+
+Partials partials(hjg_ctx* ctx) {
+  return Partials{(float*)ctx->pm.p, (double*)ctx->pS.p, (double*)ctx->pS2.p, (float*)ctx->pG.p, (float*)ctx->pZ.p};
+}
+
+// The common table of (problem, time step), generated on the caller's stream
+// unless the cached one matches; its column mean too when cv is requested.
+int ensure_table(hjg_ctx* ctx, const hjg_problem* p, int N, uint32_t step, bool need_zbar, hipStream_t s) {
+  const bool bf16 = p->sample_bf16 != 0;
+  const int64_t tstride = div_up(N, 64) * 64;
+  const bool hit = ctx->table_valid && ctx->t_seed == p->seed && ctx->t_pid == p->problem_id &&
+                   ctx->t_step == step && ctx->t_n == p->n && ctx->t_N == N && ctx->t_bf16 == (int)bf16;
+  int rc;
+  if (!hit) {
+    if ((rc = ensure(ctx, ctx->table, (size_t)p->n * tstride * (bf16 ? 2 : 4)))) return rc;
+    const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
+    HJG_HIP(launch_table(p->n, tstride, tstride, k0, k1, make_tag(p->problem_id, step, 0), bf16, ctx->table.p, s));
+    ctx->table_valid = true;
+    ctx->t_seed = p->seed;
+    ctx->t_pid = p->problem_id;
+    ctx->t_step = step;
+    ctx->t_n = p->n;
+    ctx->t_N = N;
+    ctx->t_bf16 = bf16;
+    ctx->t_stride = tstride;
+    ctx->zbar_valid = 0;
+  }
+  if (need_zbar && !ctx->zbar_valid) {
+    if ((rc = ensure(ctx, ctx->zbar, kMaxN * sizeof(double)))) return rc;
+    HJG_HIP(launch_zbar(p->n, N, ctx->t_stride, bf16, ctx->table.p, (double*)ctx->zbar.p, s));
+    ctx->zbar_valid = 1;
+  }
+  return HJG_OK;
+}
+
+int check_common(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, double t, int32_t N, uint32_t step) {
+  if (!ctx) return fail(HJG_EINVAL, "context is NULL");
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (Q < 0 || Q > (int64_t)1 << 30) return fail(HJG_EINVAL, "Q must be in [0, 2^30]");
+  if (!finite_pos(t)) return fail(HJG_EINVAL, "t must be finite and > 0");
+  if (N < 1 || N > (1 << 30)) return fail(HJG_EINVAL, "N must be in [1, 2^30]");
+  if (step >= 256) return fail(HJG_EINVAL, "time_step must be < 256");
+  return HJG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hjg_last_error(void) { return g_err.c_str(); }
+
+const char* hjg_version(void) { return "hjg 0.1 (gfx950)"; }
+
+int hjg_ctx_create(int device, hjg_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(HJG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HJG_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(HJG_EINVAL, "device index out of range");
+  HJG_HIP(hipSetDevice(device));
+  hjg_ctx* ctx = new hjg_ctx();
+  ctx->device = device;
+  if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return fail(HJG_EHIP, "cannot create the graph-recording stream");
+  }
+  *out = ctx;
+  return HJG_OK;
+}
+
+void hjg_ctx_destroy(hjg_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  drop_graphs(ctx);
+  for (DevBuf* b : {&ctx->pm, &ctx->pS, &ctx->pS2, &ctx->pG, &ctx->pZ, &ctx->vprev, &ctx->cwork, &ctx->thwork,
+                    &ctx->blockpart, &ctx->resid, &ctx->ctrl, &ctx->table, &ctx->zbar})
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  delete ctx;
+}
+
+int hjg_philox4x32_10(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G, uint32_t* out,
+                      void* hip_stream) {
+  g_err.clear();
+  if (G < 0) return fail(HJG_EINVAL, "G must be >= 0");
+  if (G == 0) return HJG_OK;
+  if (!out) return fail(HJG_EINVAL, "out is NULL");
+  HJG_HIP(launch_philox_words((uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), c1, c2, c3, G, out,
+                              (hipStream_t)hip_stream));
+  return HJG_OK;
+}
+
+int hjg_sample_table(hjg_ctx* ctx, const hjg_problem* p, int32_t N, uint32_t step, void* out, void* hip_stream) {
+  g_err.clear();
+  int rc = check_common(ctx, p, 0, 1.0, N, step);
+  if (rc) return rc;
+  if (!out) return fail(HJG_EINVAL, "out is NULL");
+  HJG_HIP(hipSetDevice(ctx->device));
+  const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
+  HJG_HIP(launch_table(p->n, N, N, k0, k1, make_tag(p->problem_id, step, 0), p->sample_bf16 != 0, out,
+                       (hipStream_t)hip_stream));
+  return HJG_OK;
+}
+
+int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N,
+                   uint32_t step, uint32_t iter, const float* c, const float* theta, float* v, float* grad,
+                   float* ess, int32_t check_finite, void* hip_stream) {
+  g_err.clear();
+  int rc = check_common(ctx, p, Q, t, N, step);
+  if (rc) return rc;
+  if (iter >= 256) return fail(HJG_EINVAL, "iter must be < 256");
+  if (Q == 0) return HJG_OK;
+  if (!x || !c || !v || !grad) return fail(HJG_EINVAL, "x, c, v and grad are required");
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool fresh = p->sample_mode == HJG_S_FRESH;
+  const Plan pl = plan_splits(Q, N, fresh);
+  if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
+  if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
+  const float sigma = (float)std::sqrt(2.0 * p->nu * t);
+
+  SweepArgs a{};
+  a.n = p->n;
+  a.Q = Q;
+  a.N = N;
+  a.ns = pl.ns;
+  a.splits = pl.splits;
+  a.x = x;
+  a.c = c;
+  a.theta = theta;
+  a.sigma = sigma;
+  a.table = fresh ? nullptr : ctx->table.p;
+  a.tstride = ctx->t_stride;
+  a.dp = datum_params(p);
+  a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(p->seed >> 32);
+  a.tag = make_tag(p->problem_id, step, iter);
+  a.cv = p->grad_cv;
+  a.part = partials(ctx);
+  a.done = nullptr;
+  HJG_HIP(launch_sweep(a, fresh, p->sample_bf16 != 0, s));
+
+  FinalizeArgs f{};
+  f.n = p->n;
+  f.Q = Q;
+  f.N = N;
+  f.splits = pl.splits;
+  f.sigma = sigma;
+  f.x = x;
+  f.c = c;
+  f.theta = theta;
+  f.part = a.part;
+  f.cv = p->grad_cv;
+  f.fresh = fresh;
+  f.zbar_tab = (const double*)ctx->zbar.p;
+  f.v = v;
+  f.grad = grad;
+  f.ess = ess;
+  f.picard = 0;
+  f.hp = ham_params(p);
+  HJG_HIP(launch_finalize(f, s));
+
+  if (check_finite) {
+    if ((rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int)))) return rc;
+    int* flag = (int*)ctx->ctrl.p + 2;
+    HJG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    HJG_HIP(launch_finite_check(v, Q, flag, s));
+    HJG_HIP(launch_finite_check(grad, Q * p->n, flag, s));
+    int host = 0;
+    HJG_HIP(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HJG_HIP(hipStreamSynchronize(s));
+    if (host) return fail(HJG_ENONFINITE, "non-finite value in v or grad");
+  }
+  return HJG_OK;
+}
+
+namespace {
+
+// Everything a recorded Picard graph depends on.
+struct PicardKey {
+  hjg_problem p;
+  int64_t Q;
+  const float* x;
+  double t;
+  int32_t N, K;
+  double tol;
+  uint32_t step;
+  const float *p0;
+  float *v, *grad, *c_out, *ess;
+  uint8_t* flags;
+  void* table;
+  int splits, ns;
+};
+
+// Field-by-field copy into zeroed storage so padding bytes never differ.
+void copy_problem(hjg_problem* dst, const hjg_problem* src) {
+  std::memset(dst, 0, sizeof(*dst));
+  dst->n = src->n;
+  dst->ham = src->ham;
+  dst->datum = src->datum;
+  for (int i = 0; i < 4; ++i) {
+    dst->ham_p[i] = src->ham_p[i];
+    dst->datum_p[i] = src->datum_p[i];
+  }
+  dst->datum_aux = src->datum_aux;
+  dst->nu = src->nu;
+  dst->eta = src->eta;
+  dst->c_min = src->c_min;
+  dst->c_max = src->c_max;
+  dst->tilt = src->tilt;
+  dst->sample_mode = src->sample_mode;
+  dst->sample_bf16 = src->sample_bf16;
+  dst->grad_cv = src->grad_cv;
+  dst->seed = src->seed;
+  dst->problem_id = src->problem_id;
+}
+
+int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
+  const hjg_problem* p = &k.p;
+  const bool fresh = p->sample_mode == HJG_S_FRESH;
+  const float sigma = (float)std::sqrt(2.0 * p->nu * k.t);
+  const int64_t Q = k.Q;
+  const int nblocks = (int)div_up(Q, kThreads);
+  int* done = (int*)ctx->ctrl.p;
+  int* iters = done + 1;
+  float* th = p->tilt ? (float*)ctx->thwork.p : nullptr;
+
+  InitArgs in{};
+  in.n = p->n;
+  in.Q = Q;
+  in.K = k.K;
+  in.sigma = sigma;
+  in.x = k.x;
+  in.p0 = k.p0;
+  in.dp = datum_params(p);
+  in.hp = ham_params(p);
+  in.tilt = p->tilt;
+  in.vprev = (float*)ctx->vprev.p;
+  in.p = k.grad;
+  in.c = (float*)ctx->cwork.p;
+  in.th = th;
+  in.done = done;
+  in.iters = iters;
+  in.resid = (double*)ctx->resid.p;
+  HJG_HIP(launch_init(in, s));
+
+  for (int it = 0; it < k.K; ++it) {
+    SweepArgs a{};
+    a.n = p->n;
+    a.Q = Q;
+    a.N = k.N;
+    a.ns = k.ns;
+    a.splits = k.splits;
+    a.x = k.x;
+    a.c = (const float*)ctx->cwork.p;
+    a.theta = th;
+    a.sigma = sigma;
+    a.table = fresh ? nullptr : ctx->table.p;
+    a.tstride = ctx->t_stride;
+    a.dp = in.dp;
+    a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(p->seed >> 32);
+    a.tag = make_tag(p->problem_id, k.step, fresh ? (uint32_t)it : 0u);
+    a.cv = p->grad_cv;
+    a.part = partials(ctx);
+    a.done = done;
+    HJG_HIP(launch_sweep(a, fresh, p->sample_bf16 != 0, s));
+
+    FinalizeArgs f{};
+    f.n = p->n;
+    f.Q = Q;
+    f.N = k.N;
+    f.splits = k.splits;
+    f.sigma = sigma;
+    f.x = k.x;
+    f.c = (const float*)ctx->cwork.p;
+    f.theta = th;
+    f.part = a.part;
+    f.cv = p->grad_cv;
+    f.fresh = fresh;
+    f.zbar_tab = (const double*)ctx->zbar.p;
+    f.v = k.v;
+    f.grad = k.grad;
+    f.ess = k.ess;
+    f.picard = 1;
+    f.vprev = (float*)ctx->vprev.p;
+    f.c_out = k.c_out;
+    f.flags = k.flags;
+    f.tol = (float)k.tol;
+    f.vfloor = (float)(1e-2 * std::sqrt(2.0 * p->nu * k.t) * std::sqrt((double)p->n));
+    f.blockpart = (double*)ctx->blockpart.p;
+    f.c_next = (float*)ctx->cwork.p;
+    f.th_next = th;
+    f.hp = in.hp;
+    f.done = done;
+    HJG_HIP(launch_finalize(f, s));
+
+    ReduceArgs r{};
+    r.nblocks = nblocks;
+    r.blockpart = (const double*)ctx->blockpart.p;
+    r.k = it;
+    r.tol = (float)k.tol;
+    r.resid = (double*)ctx->resid.p;
+    r.done = done;
+    r.iters = iters;
+    HJG_HIP(launch_reduce(r, s));
+  }
+  return HJG_OK;
+}
+
+}  // namespace
+
+int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N, int32_t K,
+                     double tol, uint32_t step, const float* p0, float* v, float* grad, float* c_out, float* ess,
+                     uint8_t* flags, double* resid_hist, int32_t* iters_done, void* hip_stream) {
+  g_err.clear();
+  int rc = check_common(ctx, p, Q, t, N, step);
+  if (rc) return rc;
+  if (K < 1 || K > 255) return fail(HJG_EINVAL, "K must be in [1, 255]");
+  if (!std::isfinite(tol)) return fail(HJG_EINVAL, "tol must be finite");
+  if (Q == 0) {
+    if (iters_done) *iters_done = 0;
+    if (resid_hist) std::fill(resid_hist, resid_hist + K, 0.0);
+    return HJG_OK;
+  }
+  if (!x || !v || !grad) return fail(HJG_EINVAL, "x, v and grad are required");
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool fresh = p->sample_mode == HJG_S_FRESH;
+  const Plan pl = plan_splits(Q, N, fresh);
+  if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
+  if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
+  if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
+  if (p->tilt && (rc = ensure(ctx, ctx->thwork, (size_t)Q * p->n * sizeof(float)))) return rc;
+  if ((rc = ensure(ctx, ctx->blockpart, (size_t)div_up(Q, kThreads) * 2 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->resid, 256 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int)))) return rc;
+  if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
+
+  PicardKey key;
+  std::memset(&key, 0, sizeof(key));
+  copy_problem(&key.p, p);
+  key.Q = Q;
+  key.x = x;
+  key.t = t;
+  key.N = N;
+  key.K = K;
+  key.tol = tol;
+  key.step = step;
+  key.p0 = p0;
+  key.v = v;
+  key.grad = grad;
+  key.c_out = c_out;
+  key.ess = ess;
+  key.flags = flags;
+  key.table = fresh ? nullptr : ctx->table.p;
+  key.splits = pl.splits;
+  key.ns = pl.ns;
+
+  const char* ng = std::getenv("HJG_NO_GRAPH");
+  if (ng && ng[0] == '1') {
+    if ((rc = record_picard(ctx, key, s))) return rc;
+  } else {
+    std::vector<char> kb(sizeof(key));
+    std::memcpy(kb.data(), &key, sizeof(key));
+    hjg_ctx::Graph* found = nullptr;
+    for (auto& g : ctx->graphs)
+      if (g.key == kb) found = &g;
+    if (!found) {
+      if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        (void)hipGraphDestroy(ctx->graphs.front().graph);
+        ctx->graphs.erase(ctx->graphs.begin());
+      }
+      HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+      rc = record_picard(ctx, key, ctx->cap);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(HJG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(HJG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+      }
+      ctx->graphs.push_back(hjg_ctx::Graph{kb, graph, exec});
+      found = &ctx->graphs.back();
+    }
+    HJG_HIP(hipGraphLaunch(found->exec, s));
+  }
+
+  if (resid_hist || iters_done || tol > 0) {
+    int ctrl[2] = {0, 0};
+    HJG_HIP(hipMemcpyAsync(ctrl, ctx->ctrl.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (resid_hist) HJG_HIP(hipMemcpyAsync(resid_hist, ctx->resid.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
+    HJG_HIP(hipStreamSynchronize(s));
+    if (iters_done) *iters_done = ctrl[1];
+    if (tol > 0 && !ctrl[0]) {
+      g_err = "tolerance not reached within K iterations";
+      return HJG_ENOTCONVERGED;
+    }
+  }
+  return HJG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Kernel arguments and launchers of the sweep (host <-> kernel boundary inside
+// the library; not part of the public C interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace hjg {
+
+constexpr int kThreads = 256;   // threads per block; one query per thread
+constexpr int kBlk = 128;       // samples staged in LDS per round (CRN)
+
+// Partial sums of one (query, sample split), all relative to the split's
+// running maximum m of the log2-weights:
+//   pm  [s][Q] float    m (log2 units)
+//   pS  [s][Q] double   sum 2^(a - m)
+//   pS2 [s][Q] double   sum 2^(2(a - m))
+//   pG  [s][n][Q] float sum 2^(a - m) z
+//   pZ  [s][n][Q] float sum z          (FRESH with control variate only)
+struct Partials {
+  float* m;
+  double* S;
+  double* S2;
+  float* G;
+  float* Z;
+};
+
+struct SweepArgs {
+  int n;
+  int64_t Q;
+  int N;
+  int ns;          // samples per split
+  int splits;
+  const float* x;      // [n][Q]
+  const float* c;      // [Q]
+  const float* theta;  // [n][Q] or nullptr
+  float sigma;
+  const void* table;   // [n][tstride] float32 or bf16 bits (CRN)
+  int64_t tstride;
+  DatumP dp;
+  uint32_t k0, k1, tag;  // Philox key and tag (FRESH)
+  int cv;                // FRESH: also accumulate sum z
+  Partials part;
+  const int* done;       // Picard stop flag or nullptr
+};
+
+struct FinalizeArgs {
+  int n;
+  int64_t Q;
+  int N;
+  int splits;
+  float sigma;
+  const float* x;
+  const float* c;        // coefficient used by the sweep  [Q]
+  const float* theta;    // shift used by the sweep [n][Q] or nullptr
+  Partials part;
+  int cv;                // subtract zbar
+  int fresh;             // zbar per query from part.Z, else from zbar_tab
+  const double* zbar_tab;  // [n] mean of the common table
+  float* v;
+  float* grad;
+  float* ess;            // or nullptr
+  // Picard bookkeeping (picard != 0)
+  int picard;
+  float* vprev;          // [Q] in: v^(k), out: v^(k+1)
+  float* c_out;          // [Q] or nullptr
+  uint8_t* flags;        // [Q] or nullptr
+  float tol;
+  float vfloor;
+  double* blockpart;     // [gridDim.x][2]: sum dv^2, sum vprev^2
+  float* c_next;         // [Q] (may alias c)
+  float* th_next;        // [n][Q] (may alias theta) or nullptr
+  HamP hp;
+  const int* done;
+};
+
+struct InitArgs {
+  int n;
+  int64_t Q;
+  int K;
+  float sigma;
+  const float* x;
+  const float* p0;       // warm start or nullptr
+  DatumP dp;
+  HamP hp;
+  int tilt;
+  float* vprev;
+  float* p;              // [n][Q] gradient iterate (the caller's grad buffer)
+  float* c;
+  float* th;             // or nullptr
+  int* done;
+  int* iters;
+  double* resid;         // [K]
+};
+
+struct ReduceArgs {
+  int nblocks;
+  const double* blockpart;
+  int k;
+  float tol;
+  double* resid;
+  int* done;
+  int* iters;
+};
+
+hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_table(int n, int64_t limit, int64_t tstride, uint32_t k0, uint32_t k1, uint32_t tag, int bf16,
+                        void* out, hipStream_t s);
+hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s);
+hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G,
+                               uint32_t* out, hipStream_t s);
+hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
+
+// Smallest register bucket that holds n dimensions.
+inline int n_bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 48; }
+
+}  // namespace hjg

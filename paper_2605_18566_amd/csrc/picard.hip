@@ -1,0 +1,287 @@
+// Per-query kernels around the pair loop: draw tables, Picard initialisation,
+// the float64 merge of sample splits with the estimator formulas, the Picard
+// update of coefficient and shift, and the residual reduction.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace hjg {
+
+hipError_t launch_sweep_half_sqnorm(const SweepArgs&, int, int, hipStream_t);
+hipError_t launch_sweep_ball(const SweepArgs&, int, int, hipStream_t);
+hipError_t launch_sweep_min_pair_disks(const SweepArgs&, int, int, hipStream_t);
+hipError_t launch_sweep_knn_balls(const SweepArgs&, int, int, hipStream_t);
+hipError_t launch_sweep_linear(const SweepArgs&, int, int, hipStream_t);
+
+hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+  switch (a.dp.kind) {
+    case HJG_L_HALF_SQNORM: return launch_sweep_half_sqnorm(a, fresh, bf16, s);
+    case HJG_L_BALL: return launch_sweep_ball(a, fresh, bf16, s);
+    case HJG_L_MIN_PAIR_DISKS: return launch_sweep_min_pair_disks(a, fresh, bf16, s);
+    case HJG_L_KNN_BALLS: return launch_sweep_knn_balls(a, fresh, bf16, s);
+    case HJG_L_LINEAR: return launch_sweep_linear(a, fresh, bf16, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+namespace {
+
+constexpr uint32_t kCrnStream = 0xFFFFFFFFu;
+
+// ------------------------------------------------------------------ draw table
+// z[d][i] for d < n, i < limit, row stride tstride (>= limit).
+__global__ __launch_bounds__(kThreads) void table_kernel(int n, int64_t limit, int64_t tstride, uint32_t k0,
+                                                         uint32_t k1, uint32_t tag, int bf16, void* out) {
+  const int64_t groups = (limit + 3) / 4;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= groups * n) return;
+  const int d = (int)(idx / groups);
+  const int64_t g = idx % groups;
+  float z[4];
+  normals4((uint32_t)g, (uint32_t)d, kCrnStream, tag, k0, k1, z);
+  const int64_t base = (int64_t)d * tstride + 4 * g;
+  if (bf16) {
+    uint16_t* o = static_cast<uint16_t*>(out);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) if (4 * g + j < limit) o[base + j] = f32_to_bf16_rne(z[j]);
+  } else {
+    float* o = static_cast<float*>(out);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) if (4 * g + j < limit) o[base + j] = z[j];
+  }
+}
+
+// zbar[d] = (1/N) sum_{i<N} z[d][i] in float64, one block per dimension,
+// fixed reduction order (deterministic).
+__global__ __launch_bounds__(kThreads) void zbar_kernel(int N, int64_t tstride, int bf16, const void* table,
+                                                        double* zbar) {
+  const int d = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    const int64_t idx = (int64_t)d * tstride + i;
+    s += bf16 ? (double)bf16_to_f32(static_cast<const uint16_t*>(table)[idx])
+              : (double)static_cast<const float*>(table)[idx];
+  }
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) zbar[d] = red[0] / (double)N;
+}
+
+__global__ __launch_bounds__(kThreads) void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2,
+                                                                uint32_t c3, int64_t G, uint32_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x; g < G; g += stride) {
+    const U4 w = philox4x32_10(U4{(uint32_t)g, c1, c2, c3}, k0, k1);
+    out[4 * g + 0] = w.x;
+    out[4 * g + 1] = w.y;
+    out[4 * g + 2] = w.z;
+    out[4 * g + 3] = w.w;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void finite_kernel(const float* a, int64_t count, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += stride) bad |= !isfinite(a[i]);
+  if (bad) *flag = 1;   // benign race: every writer stores 1
+}
+
+// ------------------------------------------------------------ Picard start
+template <int NM>
+__global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) {
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < I.K; k += kThreads) I.resid[k] = 0.0;
+    if (threadIdx.x == 0) { *I.done = 0; *I.iters = 0; }
+  }
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= I.Q) return;
+  float x[NM], g[NM];
+#pragma unroll
+  for (int d = 0; d < NM; ++d) x[d] = d < I.n ? I.x[(int64_t)d * I.Q + q] : 0.f;
+  const float l = datum_and_grad<NM>(I.dp, x, g, q, I.Q);
+  I.vprev[q] = l;                                   // v^(0) = l(x)
+  if (I.p0) {
+#pragma unroll
+    for (int d = 0; d < NM; ++d) g[d] = d < I.n ? I.p0[(int64_t)d * I.Q + q] : 0.f;
+  }
+#pragma unroll
+  for (int d = 0; d < NM; ++d) if (d < I.n) I.p[(int64_t)d * I.Q + q] = g[d];
+  const float c = coefficient<NM>(I.hp, x, g);       // c^(0) from D l (or the warm start)
+  I.c[q] = c;
+  if (I.th) {
+    const float s2c = -I.sigma * I.sigma * c;
+#pragma unroll
+    for (int d = 0; d < NM; ++d) if (d < I.n) I.th[(int64_t)d * I.Q + q] = s2c * g[d];
+  }
+}
+
+// ------------------------------------------------------------ finalize
+// Merge the split partials in float64 (max-rescaled sums), then
+//   v = -(m ln 2 + ln(S/N)) / c,  Dv = -(theta + sigma (G/S - [zbar])) / (c sigma^2),
+//   ESS = S^2 / S2,
+// and, inside the Picard loop, the residual terms, the per-query flag and the
+// next coefficient and shift from p = Dv.
+template <int NM>
+__global__ __launch_bounds__(kThreads) void finalize_kernel(FinalizeArgs F) {
+  if (F.done && *F.done) return;
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool active = q < F.Q;
+  double dv2 = 0.0, vp2 = 0.0;
+  if (active) {
+    const int64_t Q = F.Q;
+    double M = -INFINITY;
+    for (int s = 0; s < F.splits; ++s) M = fmax(M, (double)F.part.m[(int64_t)s * Q + q]);
+    double S = 0.0, S2 = 0.0;
+    for (int s = 0; s < F.splits; ++s) {
+      const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
+      S += F.part.S[(int64_t)s * Q + q] * f;
+      S2 += F.part.S2[(int64_t)s * Q + q] * f * f;
+    }
+    const double c = (double)F.c[q];
+    const double sg = (double)F.sigma;
+    const double v = -(M * kLn2 + log(S / (double)F.N)) / c;
+    float xq[NM], pg[NM];
+#pragma unroll
+    for (int d = 0; d < NM; ++d) {
+      xq[d] = 0.f;
+      pg[d] = 0.f;
+      if (d < F.n) {
+        double G = 0.0, Z = 0.0;
+        for (int s = 0; s < F.splits; ++s) {
+          const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
+          const int64_t idx = ((int64_t)s * F.n + d) * Q + q;
+          G += (double)F.part.G[idx] * f;
+          if (F.cv && F.fresh) Z += (double)F.part.Z[idx];
+        }
+        double gbar = G / S;
+        if (F.cv) gbar -= F.fresh ? Z / (double)F.N : F.zbar_tab[d];
+        const double th = F.theta ? (double)F.theta[(int64_t)d * Q + q] : 0.0;
+        const double gr = -(th + sg * gbar) / (c * sg * sg);
+        pg[d] = (float)gr;
+        F.grad[(int64_t)d * Q + q] = pg[d];
+        xq[d] = F.x[(int64_t)d * Q + q];
+      }
+    }
+    const float vf = (float)v;
+    F.v[q] = vf;
+    if (F.ess) F.ess[q] = (float)(S * S / S2);
+    if (F.picard) {
+      const float vp = F.vprev[q];
+      const float dv = vf - vp;
+      dv2 = (double)dv * (double)dv;
+      vp2 = (double)vp * (double)vp;
+      if (F.flags) F.flags[q] = (fabsf(dv) / fmaxf(fabsf(vp), F.vfloor)) > F.tol ? 1 : 0;
+      F.vprev[q] = vf;
+      if (F.c_out) F.c_out[q] = F.c[q];
+      const float cn = coefficient<NM>(F.hp, xq, pg);
+      if (F.th_next) {
+        const float s2c = -F.sigma * F.sigma * cn;
+#pragma unroll
+        for (int d = 0; d < NM; ++d) if (d < F.n) F.th_next[(int64_t)d * Q + q] = s2c * pg[d];
+      }
+      F.c_next[q] = cn;
+    }
+  }
+  if (F.picard) {
+    for (int off = 32; off > 0; off >>= 1) {
+      dv2 += __shfl_down(dv2, off, 64);
+      vp2 += __shfl_down(vp2, off, 64);
+    }
+    __shared__ double red[2][kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wid] = dv2; red[1][wid] = vp2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) { a += red[0][w]; b += red[1][w]; }
+      F.blockpart[2 * blockIdx.x] = a;
+      F.blockpart[2 * blockIdx.x + 1] = b;
+    }
+  }
+}
+
+// Relative L2 change over all queries from the block partials (float64, fixed order).
+__global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs R) {
+  if (*R.done) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < R.nblocks; i += kThreads) { a += R.blockpart[2 * i]; b += R.blockpart[2 * i + 1]; }
+  __shared__ double ra[kThreads], rb[kThreads];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) { ra[threadIdx.x] += ra[threadIdx.x + off]; rb[threadIdx.x] += rb[threadIdx.x + off]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double num = sqrt(ra[0]), den = sqrt(rb[0]);
+    const double r = den > 0.0 ? num / den : num;
+    R.resid[R.k] = r;
+    *R.iters = R.k + 1;
+    if (r < (double)R.tol) *R.done = 1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_table(int n, int64_t limit, int64_t tstride, uint32_t k0, uint32_t k1, uint32_t tag, int bf16,
+                        void* out, hipStream_t s) {
+  const int64_t work = ((limit + 3) / 4) * n;
+  table_kernel<<<(unsigned)((work + kThreads - 1) / kThreads), kThreads, 0, s>>>(n, limit, tstride, k0, k1, tag,
+                                                                                  bf16, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s) {
+  zbar_kernel<<<n, kThreads, 0, s>>>(N, tstride, bf16, table, zbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G,
+                               uint32_t* out, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((G + kThreads - 1) / kThreads, 65536);
+  philox_words_kernel<<<(unsigned)std::max<int64_t>(blocks, 1), kThreads, 0, s>>>(k0, k1, c1, c2, c3, G, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((count + kThreads - 1) / kThreads, 4096);
+  finite_kernel<<<(unsigned)std::max<int64_t>(blocks, 1), kThreads, 0, s>>>(a, count, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)std::max<int64_t>((a.Q + kThreads - 1) / kThreads, 1));
+  switch (n_bucket(a.n)) {
+    case 4: init_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
+    case 8: init_kernel<8><<<grid, kThreads, 0, s>>>(a); break;
+    case 16: init_kernel<16><<<grid, kThreads, 0, s>>>(a); break;
+    case 32: init_kernel<32><<<grid, kThreads, 0, s>>>(a); break;
+    default: init_kernel<48><<<grid, kThreads, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads));
+  switch (n_bucket(a.n)) {
+    case 4: finalize_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
+    case 8: finalize_kernel<8><<<grid, kThreads, 0, s>>>(a); break;
+    case 16: finalize_kernel<16><<<grid, kThreads, 0, s>>>(a); break;
+    case 32: finalize_kernel<32><<<grid, kThreads, 0, s>>>(a); break;
+    default: finalize_kernel<48><<<grid, kThreads, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  reduce_kernel<<<1, kThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace hjg

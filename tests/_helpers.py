@@ -1,0 +1,52 @@
+"""Test helpers: the same problem described to the oracle and to the library,
+and the parity tolerances."""
+from __future__ import annotations
+
+import numpy as np
+
+U32 = 2.0 ** -24          # float32 unit roundoff
+
+
+def oracle_problem(fields: dict, aux=None):
+    from oracle import model
+    f = dict(fields)
+    return model.Problem(datum_aux=aux, **f)
+
+
+def gpu_problem(fields: dict, aux=None, problem_id: int = 0):
+    from paper_2605_18566_amd import ProblemSpec
+    return ProblemSpec(datum_aux=aux, problem_id=problem_id, **fields)
+
+
+def to_dev(a: np.ndarray, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+
+
+def soa(x: np.ndarray) -> np.ndarray:
+    """[Q, n] -> [n, Q] float32."""
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float32).T)
+
+
+def value_tol(v_or, c, theta, sigma, lmax):
+    """Value tolerance: 1e-4 |v| plus a float32 rounding floor.
+
+    The device forms the log-weight a = -c l(y) - |theta|^2/(2 sigma^2)
+    - <z, theta>/sigma in float32; each term carries a relative rounding of a
+    few u32, so |delta a| <~ k u32 |c| L with
+    L = max|l(y)| + |theta|^2/(2 sigma^2 |c|) + |theta| |z|max/(sigma |c|),
+    and v = -(1/c) log mean e^a moves by |delta a|/|c| <= k u32 L.  The sums
+    S are float32 within one 128-sample LDS round (relative error <= 128 u32)
+    and float64 across rounds, giving another 128 u32/|c|.  k = 64 covers the
+    number of roundings on the path with margin.
+    """
+    c = np.abs(np.asarray(c, dtype=np.float64))
+    th2 = np.sum(np.asarray(theta, dtype=np.float64) ** 2, axis=-1) if theta is not None else 0.0
+    L = lmax + th2 / (2 * sigma ** 2 * c) + np.sqrt(th2) * 6.0 / (sigma * c)
+    return 1e-4 * np.abs(v_or) + 64 * U32 * (1.0 + L) + 128 * U32 / c
+
+
+def grad_tol(g_or, c, sigma, N):
+    """Gradient tolerance: 1e-3 max(|Dv|, 1/(|c| sigma sqrt(N))) per query (2-norm)."""
+    gn = np.linalg.norm(g_or, axis=-1)
+    return 1e-3 * np.maximum(gn, 1.0 / (np.abs(c) * sigma * np.sqrt(N)))

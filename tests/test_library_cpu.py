@@ -1,0 +1,84 @@
+"""The C interface library builds for gfx950, loads, exports every declared
+entry point, and rejects bad arguments before touching a device (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(hjg_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_18566_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2605_18566_amd.build import build
+        build()
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2605_18566_amd import _lib
+    assert {s[0] for s in _lib.SIGNATURES} == set(names)
+
+
+def test_struct_layout_matches_header(lib, tmp_path):
+    import shutil
+    import subprocess
+    from paper_2605_18566_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hjg.h"\nint main(){printf("%zu %zu %zu %zu\\n",'
+                   'sizeof(hjg_problem), offsetof(hjg_problem, datum_aux), offsetof(hjg_problem, seed),'
+                   'offsetof(hjg_problem, problem_id));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(_lib.Problem), _lib.Problem.datum_aux.offset, _lib.Problem.seed.offset,
+                   _lib.Problem.problem_id.offset]
+
+
+def test_version_and_error_paths_without_device(lib):
+    from paper_2605_18566_amd import _lib
+    assert lib.hjg_version().startswith(b"hjg")
+    assert lib.hjg_philox4x32_10(0, 0, 0, 0, 0, None, None) == _lib.HJG_OK          # G = 0: no launch
+    assert lib.hjg_philox4x32_10(0, 0, 0, 0, -1, None, None) == _lib.HJG_EINVAL
+    p = _lib.Problem()
+    p.n, p.nu, p.c_min, p.c_max = 2, 0.05, 0.01, 1e4
+    rc = lib.hjg_value_grad(None, C.byref(p), 4, None, 0.5, 16, 0, 0, None, None, None, None, None, 0, None)
+    assert rc == _lib.HJG_EINVAL and b"context" in lib.hjg_last_error()
+    rc = lib.hjg_picard_sweep(None, C.byref(p), 4, None, 0.5, 16, 1, 0.0, 0, None, None, None, None, None, None,
+                              None, None, None)
+    assert rc == _lib.HJG_EINVAL
+    lib.hjg_ctx_destroy(None)
+
+
+def test_kernels_are_gfx950_code_objects(lib):
+    from paper_2605_18566_amd import _lib
+    blob = open(_lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2605_18566_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        _lib.lib()

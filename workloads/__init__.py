@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+Holds workload parameters and query generators only -- none of the method's
+arithmetic.  Queries come from numpy's PCG64 stream seeded with
+[2605, 18566, config, trial]; the Philox key of a workload is
+0x0002605185660000 + 16 config + trial.  All inputs are synthetic with the
+shapes, sizes and distributions of the workloads they stand for (the paper
+measures on no public dataset).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+PI = math.pi
+
+
+def rng(cfg: int, trial: int = 0) -> np.random.Generator:
+    return np.random.default_rng([2605, 18566, cfg, trial])
+
+
+def philox_seed(cfg: int, trial: int = 0) -> int:
+    return 0x0002605185660000 + 16 * cfg + trial
+
+
+@dataclass
+class Workload:
+    """Parameters of one sweep workload (the fields of the problem record plus sizes)."""
+    name: str
+    n: int
+    ham: str
+    datum: str
+    nu: float
+    t: float
+    Q: int
+    N: int
+    K: int
+    box: Tuple[Tuple[float, float], ...]
+    ham_p: Tuple[float, ...] = (1.0, 1.0, 1.0, 1.0)
+    datum_p: Tuple[float, ...] = ()
+    eta: float = 1e-2
+    c_min: float = 1e-2
+    c_max: float = 1e4
+    tilt: bool = False
+    sample_mode: str = "crn_step"
+    sample_bf16: bool = False
+    grad_cv: bool = False
+    cfg: int = 0
+    time_steps: int = 1
+    T: float = 1.0
+
+    @property
+    def seed(self) -> int:
+        return philox_seed(self.cfg)
+
+    def resized(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    def problem_fields(self) -> dict:
+        return dict(n=self.n, ham=self.ham, datum=self.datum, nu=self.nu, ham_p=tuple(self.ham_p),
+                    datum_p=tuple(self.datum_p), eta=self.eta, c_min=self.c_min, c_max=self.c_max,
+                    tilt=self.tilt, sample_mode=self.sample_mode, sample_bf16=self.sample_bf16,
+                    grad_cv=self.grad_cv, seed=self.seed)
+
+
+def queries(w: Workload, Q: Optional[int] = None, trial: int = 0) -> np.ndarray:
+    """Uniform queries in the workload's box, float32 [Q, n]."""
+    Q = w.Q if Q is None else Q
+    g = rng(w.cfg, trial)
+    lo = np.array([b[0] for b in w.box])
+    hi = np.array([b[1] for b in w.box])
+    return (lo + (hi - lo) * g.random((Q, w.n))).astype(np.float32)
+
+
+def dubins_box(m: int):
+    return tuple([(-3.0, 3.0), (-3.0, 3.0), (-PI, PI)] * m)
+
+
+# Plain MC, n = 2, H = |p|^2/2, nu = 0.05, t = 0.5, disk SDF; 4,096 queries in
+# [-2, 2]^2, N = 8,192 draws per query, one Picard iteration.
+C1 = Workload("c1_quadratic_disk_n2", n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=0.05, t=0.5,
+              Q=4096, N=8192, K=1, box=((-2.0, 2.0), (-2.0, 2.0)), sample_mode="fresh", cfg=1)
+C1_QUAD = replace(C1, name="c1_quadratic_halfsq_n2", datum="half_sqnorm", datum_p=())
+
+# Dubins pursuit-evasion in relative coordinates, disk of radius 0.5, nu = 0.01,
+# T = 1 in 10 horizons, 5 iterations, 65,536 queries, N = 65,536 common draws.
+C2 = Workload("c2_dubins_n3", n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01, t=1.0,
+              Q=65536, N=65536, K=5, box=dubins_box(1), tilt=True, sample_mode="crn_step", cfg=2,
+              time_steps=10, T=1.0)
+
+# n = 45: 15 stacked relative Dubins pairs, nu = 0.01, T = 1, bfloat16 common
+# draws, N = 65,536, K = 5, 262,144 queries (the surrogate's inference size).
+C5 = Workload("c5_dubins15_n45", n=45, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
+              t=1.0, Q=262144, N=65536, K=5, box=dubins_box(15), tilt=True, sample_mode="crn_step",
+              sample_bf16=True, cfg=5)
+
+
+def horizons(w: Workload):
+    """Time-to-go of each horizon: t_j = j T / S_t, j = 1..S_t."""
+    return [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
