@@ -1,0 +1,168 @@
+"""Throughput of the Monte-Carlo Picard sweep on one MI355X.
+
+One step = one full Picard sweep (Algorithm 1: K frozen-coefficient
+iterations, each drawing N samples per query and returning v and Dv) over the
+n = 45 workload: 15 stacked relative Dubins pairs, 262,144 queries,
+N = 65,536 bfloat16 common draws, K = 5, nu = 0.01, t = 1, Laplace shift from
+the previous iterate.  The metric is query.samples per second:
+Q * N * K / (seconds per step).
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(the pair loop, timed by HIP events around every launch inside the timed
+region) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "query·samples/s for v,∇v at n=45; surrogate vs plain MC at equal RMS error"
+
+# Chip figures used for the roofline (MI355X, gfx950).
+CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ     # 3.93e13 VALU lane-op slots / s
+
+
+def alu_slots_per_pair(datum: str, n: int) -> int:
+    """Minimum VALU lane-op slots per (query, sample) pair that are not a dense contraction.
+
+    min_pair_disks with m = n/3 pairs: per pair 2 FMA (y), MUL + FMA (|y|^2),
+    MIN -> 5m - 1; sqrt (transcendental, 2 slots) and the radius subtraction
+    -> 3; the log-weight a = -c l + (a0 - <z, theta>) -> 2; running max -> 1;
+    exp2(a - m) (sub + 2 slots) -> 3; S += w, S2 += w^2 -> 2.  Total 5m + 10.
+    The two contractions <z, theta> and sum w z (2n MACs) belong to MFMA and
+    are not counted.
+    """
+    if datum == "min_pair_disks":
+        return 5 * (n // 3) + 10
+    raise ValueError(datum)
+
+
+def cpu_oracle_baseline(w, per_worker: int, workers: int):
+    """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t0 = time.perf_counter()
+    # forked workers, started before this process touches the GPU
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        futs = [ex.submit(_oracle_chunk, w, per_worker, i) for i in range(workers)]
+        for f in futs:
+            f.result()
+    dt = time.perf_counter() - t0
+    pairs = workers * per_worker * w.N * w.K
+    return pairs / dt, dt, pairs
+
+
+def _oracle_chunk(w, q, trial):
+    import numpy as np
+
+    import workloads
+    from oracle import estimator, model
+    x = workloads.queries(w, Q=q, trial=100 + trial).astype(np.float64)
+    estimator.picard(model.Problem(**w.problem_fields()), x, w.t, w.N, w.K)
+    return q
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--queries", type=int, default=None, help="override Q (default: the workload's 262,144)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries would be split across GPUs with no exchange but a 16-byte residual "
+              "all-reduce per iteration).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import workloads
+
+    w = workloads.C5
+    if args.queries:
+        w = w.resized(Q=args.queries)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        rate, dt, pairs = cpu_oracle_baseline(w, args.cpu_queries_per_worker, workers)
+        cpu = {"value": rate, "unit": "query·samples/s", "cores": workers, "kind": "oracle",
+               "sample": f"{workers * args.cpu_queries_per_worker} queries x N={w.N} x K={w.K} of the same "
+                         f"workload ({pairs:.3g} pairs, {dt:.1f} s, one process per core)"}
+        print(f"cpu baseline: {rate:.3e} pairs/s on {workers} cores ({dt:.1f} s)", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2605_18566_amd import Context, ProblemSpec, picard_sweep
+
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to(dev)
+    spec = ProblemSpec(**w.problem_fields())
+    ctx = Context(0)
+    ctx.set_timing(True)
+    stream = torch.cuda.Stream(device=dev)
+    out = None
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            out = picard_sweep(ctx, spec, x, w.t, w.N, w.K, host_outputs=False, out=out, stream=stream)
+        torch.cuda.synchronize()
+        print("warmup done", file=sys.stderr, flush=True)
+        kernel_ms, launches = 0.0, 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = picard_sweep(ctx, spec, x, w.t, w.N, w.K, host_outputs=False, out=out, stream=stream)
+            ms, nl = ctx.sweep_time()
+            kernel_ms += ms
+            launches += nl
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    v = out.v.cpu().numpy()
+    if not np.all(np.isfinite(v)):
+        raise RuntimeError("non-finite values in the benchmark output")
+
+    sec_per_step = (t1 - t0) / args.steps
+    pairs_per_step = w.Q * w.N * w.K
+    value = pairs_per_step / sec_per_step
+    slots = alu_slots_per_pair(w.datum, w.n)
+    per_launch_ms = kernel_ms / max(launches, 1)
+    achieved = slots * w.Q * w.N / (per_launch_ms * 1e-3)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "query·samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: plain Monte-Carlo Picard sweep", "n": w.n, "queries": w.Q,
+                   "samples": w.N, "picard_iterations": w.K, "nu": w.nu, "t": w.t,
+                   "draws": "bf16 common table (Philox4x32-10)", "tilt": "Laplace shift from previous iterate",
+                   "hamiltonian": w.ham, "datum": w.datum},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK, "traffic": None,
+                     "kernel": "sweep_crn_kernel (pair loop)", "kernel_ms_per_launch": per_launch_ms,
+                     "launches_timed": launches, "alu_slots_per_pair": slots},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

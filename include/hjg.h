@@ -200,6 +200,19 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
                      float* c_out, float* ess, uint8_t* flags,
                      double* resid_hist, int32_t* iters_done, void* hip_stream);
 
+/*
+ * Kernel timing (profiling hook).  With timing enabled, every launch of the
+ * pair-loop kernel made by hjg_value_grad / hjg_picard_sweep is bracketed by
+ * HIP events on the caller's stream; while timing is on, the Picard loop is
+ * launched kernel by kernel instead of being replayed from its recorded graph
+ * (events recorded as graph nodes carry no usable timestamps).  hjg_sweep_time
+ * waits for the last such call and returns the summed pair-loop kernel time
+ * of that call (ms) and the number of launches timed.  Results are identical
+ * with timing on or off.  Returns HJG_EINVAL on NULL arguments.
+ */
+int hjg_set_timing(hjg_ctx* ctx, int32_t enable);
+int hjg_sweep_time(hjg_ctx* ctx, double* total_ms, int32_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

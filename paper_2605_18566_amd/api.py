@@ -94,6 +94,16 @@ class Context:
     def handle(self):
         return self._h
 
+    def set_timing(self, enable: bool):
+        """Bracket every pair-loop kernel launch with HIP events."""
+        check(_lib.lib().hjg_set_timing(self._h, int(bool(enable))))
+
+    def sweep_time(self):
+        """(total ms, launches) of the pair-loop kernels of the last call; waits for it."""
+        ms, n = C.c_double(0.0), C.c_int32(0)
+        check(_lib.lib().hjg_sweep_time(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().hjg_ctx_destroy(self._h)

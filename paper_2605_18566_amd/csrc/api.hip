@@ -57,7 +57,15 @@ struct hjg_ctx {
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
+  // optional timing of the pair-loop kernels: HIP events around each sweep
+  int timing = 0;
+  std::vector<hipEvent_t> ev;   // [2 * kMaxTimed]: begin/end per sweep launch
+  int last_pairs = 0;           // event pairs used by the last call
 };
+
+namespace {
+constexpr int kMaxTimed = 256;
+}
 
 namespace {
 
@@ -248,6 +256,13 @@ int ensure_table(hjg_ctx* ctx, const hjg_problem* p, int N, uint32_t step, bool 
   return HJG_OK;
 }
 
+int ensure_events(hjg_ctx* ctx) {
+  if (!ctx->ev.empty()) return HJG_OK;
+  ctx->ev.resize(2 * kMaxTimed, nullptr);
+  for (auto& e : ctx->ev) HJG_HIP(hipEventCreate(&e));
+  return HJG_OK;
+}
+
 int check_common(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, double t, int32_t N, uint32_t step) {
   if (!ctx) return fail(HJG_EINVAL, "context is NULL");
   int rc = check_problem(p);
@@ -293,6 +308,8 @@ void hjg_ctx_destroy(hjg_ctx* ctx) {
   for (DevBuf* b : {&ctx->pm, &ctx->pS, &ctx->pS2, &ctx->pG, &ctx->pZ, &ctx->vprev, &ctx->cwork, &ctx->thwork,
                     &ctx->blockpart, &ctx->resid, &ctx->ctrl, &ctx->table, &ctx->zbar})
     if (b->p) (void)hipFree(b->p);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
 }
@@ -356,7 +373,15 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   a.cv = p->grad_cv;
   a.part = partials(ctx);
   a.done = nullptr;
+  if (ctx->timing) {
+    if ((rc = ensure_events(ctx))) return rc;
+    HJG_HIP(hipEventRecord(ctx->ev[0], s));
+  }
   HJG_HIP(launch_sweep(a, fresh, p->sample_bf16 != 0, s));
+  if (ctx->timing) {
+    HJG_HIP(hipEventRecord(ctx->ev[1], s));
+    ctx->last_pairs = 1;
+  }
 
   FinalizeArgs f{};
   f.n = p->n;
@@ -408,6 +433,7 @@ struct PicardKey {
   uint8_t* flags;
   void* table;
   int splits, ns;
+  int timing;
 };
 
 // Field-by-field copy into zeroed storage so padding bytes never differ.
@@ -482,7 +508,9 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
     a.cv = p->grad_cv;
     a.part = partials(ctx);
     a.done = done;
+    if (k.timing) HJG_HIP(hipEventRecord(ctx->ev[2 * it], s));
     HJG_HIP(launch_sweep(a, fresh, p->sample_bf16 != 0, s));
+    if (k.timing) HJG_HIP(hipEventRecord(ctx->ev[2 * it + 1], s));
 
     FinalizeArgs f{};
     f.n = p->n;
@@ -574,9 +602,16 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   key.table = fresh ? nullptr : ctx->table.p;
   key.splits = pl.splits;
   key.ns = pl.ns;
+  key.timing = ctx->timing;
+  if (ctx->timing) {
+    if ((rc = ensure_events(ctx))) return rc;
+    ctx->last_pairs = K;
+  }
 
+  // With timing on, launch kernel by kernel: HIP cannot take elapsed times
+  // from events recorded as nodes of a graph.
   const char* ng = std::getenv("HJG_NO_GRAPH");
-  if (ng && ng[0] == '1') {
+  if ((ng && ng[0] == '1') || ctx->timing) {
     if ((rc = record_picard(ctx, key, s))) return rc;
   } else {
     std::vector<char> kb(sizeof(key));
@@ -622,6 +657,36 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
       return HJG_ENOTCONVERGED;
     }
   }
+  return HJG_OK;
+}
+
+int hjg_set_timing(hjg_ctx* ctx, int32_t enable) {
+  g_err.clear();
+  if (!ctx) return fail(HJG_EINVAL, "context is NULL");
+  HJG_HIP(hipSetDevice(ctx->device));
+  if (enable) {
+    const int rc = ensure_events(ctx);
+    if (rc) return rc;
+  }
+  ctx->timing = enable ? 1 : 0;
+  ctx->last_pairs = 0;
+  return HJG_OK;
+}
+
+int hjg_sweep_time(hjg_ctx* ctx, double* total_ms, int32_t* launches) {
+  g_err.clear();
+  if (!ctx || !total_ms || !launches) return fail(HJG_EINVAL, "NULL argument");
+  *total_ms = 0.0;
+  *launches = 0;
+  if (!ctx->timing || ctx->last_pairs == 0) return HJG_OK;
+  HJG_HIP(hipSetDevice(ctx->device));
+  HJG_HIP(hipEventSynchronize(ctx->ev[2 * ctx->last_pairs - 1]));
+  for (int i = 0; i < ctx->last_pairs; ++i) {
+    float ms = 0.f;
+    HJG_HIP(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+    *total_ms += ms;
+  }
+  *launches = ctx->last_pairs;
   return HJG_OK;
 }
 

@@ -271,3 +271,21 @@ def test_single_sample_and_single_query(ctx):
         v, g, e = value_grad(ctx, gpu_problem(fields), to_dev(soa(x)), 1.0, N, to_dev(c))
         np.testing.assert_allclose(v.cpu().numpy(), ref.v, rtol=1e-5, atol=1e-6)
         np.testing.assert_allclose(e.cpu().numpy(), ref.ess, rtol=1e-5)
+
+
+def test_timing_hook_keeps_results(ctx):
+    from paper_2605_18566_amd import picard_sweep
+    fields = dict(workloads.C2.problem_fields())
+    x = to_dev(soa(workloads.queries(workloads.C2, Q=800, trial=12)))
+    spec = gpu_problem(fields)
+    a = picard_sweep(ctx, spec, x, 1.0, 2048, 4)
+    ctx.set_timing(True)
+    try:
+        b = picard_sweep(ctx, spec, x, 1.0, 2048, 4)
+        ms, launches = ctx.sweep_time()
+        b2 = picard_sweep(ctx, spec, x, 1.0, 2048, 4)     # replay of the timed graph
+        ms2, launches2 = ctx.sweep_time()
+    finally:
+        ctx.set_timing(False)
+    assert launches == 4 and launches2 == 4 and ms > 0 and ms2 > 0
+    assert torch.equal(a.v, b.v) and torch.equal(a.grad, b.grad) and torch.equal(b.v, b2.v)
