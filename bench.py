@@ -157,7 +157,7 @@ def main():
                    "hamiltonian": w.ham, "datum": w.datum},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK, "traffic": None,
-                     "kernel": "sweep_crn_kernel (pair loop)", "kernel_ms_per_launch": per_launch_ms,
+                     "kernel": "pair loop (sweep_mfma_kernel<min_pair_disks, 48, 15>)", "kernel_ms_per_launch": per_launch_ms,
                      "launches_timed": launches, "alu_slots_per_pair": slots},
         "cpu_baseline": cpu,
     }

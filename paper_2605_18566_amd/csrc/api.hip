@@ -192,6 +192,14 @@ HamP ham_params(const hjg_problem* p) {
 
 uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter) { return (pid << 16) | (step << 8) | iter; }
 
+// The matrix-core pair loop serves bfloat16 common tables with n >= 16
+// (HJG_NO_MFMA=1 forces the vector-ALU loop, for comparison).
+bool use_mfma(const hjg_problem* p) {
+  const char* e = std::getenv("HJG_NO_MFMA");
+  if (e && e[0] == '1') return false;
+  return p->sample_mode == HJG_S_CRN_STEP && p->sample_bf16 && p->n >= 16 && p->datum != HJG_L_KNN_BALLS;
+}
+
 struct Plan {
   int splits;
   int ns;
@@ -199,10 +207,10 @@ struct Plan {
 
 // Cut the N samples of each query into contiguous splits so that the launch
 // has enough blocks to fill 256 CUs (about 8 resident blocks each).
-Plan plan_splits(int64_t Q, int N, bool fresh) {
+Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block) {
   int target = 2048;
   if (const char* e = std::getenv("HJG_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
-  const int64_t qblocks = div_up(Q, kThreads);
+  const int64_t qblocks = div_up(Q, queries_per_block);
   const int gran = fresh ? 64 : kBlk;
   int64_t splits = std::max<int64_t>(1, div_up(target, qblocks));
   splits = std::min<int64_t>(splits, div_up(N, gran));
@@ -349,7 +357,8 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   HJG_HIP(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
-  const Plan pl = plan_splits(Q, N, fresh);
+  const bool mf = use_mfma(p);
+  const Plan pl = plan_splits(Q, N, fresh, mf ? kQueriesPerBlockMfma : kQueriesPerBlockValu);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
   const float sigma = (float)std::sqrt(2.0 * p->nu * t);
@@ -371,6 +380,7 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   a.k1 = (uint32_t)(p->seed >> 32);
   a.tag = make_tag(p->problem_id, step, iter);
   a.cv = p->grad_cv;
+  a.mfma = mf;
   a.part = partials(ctx);
   a.done = nullptr;
   if (ctx->timing) {
@@ -434,6 +444,7 @@ struct PicardKey {
   void* table;
   int splits, ns;
   int timing;
+  int mfma;
 };
 
 // Field-by-field copy into zeroed storage so padding bytes never differ.
@@ -506,6 +517,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
     a.k1 = (uint32_t)(p->seed >> 32);
     a.tag = make_tag(p->problem_id, k.step, fresh ? (uint32_t)it : 0u);
     a.cv = p->grad_cv;
+    a.mfma = use_mfma(p);
     a.part = partials(ctx);
     a.done = done;
     if (k.timing) HJG_HIP(hipEventRecord(ctx->ev[2 * it], s));
@@ -573,7 +585,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   HJG_HIP(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
-  const Plan pl = plan_splits(Q, N, fresh);
+  const Plan pl = plan_splits(Q, N, fresh, use_mfma(p) ? kQueriesPerBlockMfma : kQueriesPerBlockValu);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
@@ -603,6 +615,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   key.splits = pl.splits;
   key.ns = pl.ns;
   key.timing = ctx->timing;
+  key.mfma = use_mfma(p);
   if (ctx->timing) {
     if ((rc = ensure_events(ctx))) return rc;
     ctx->last_pairs = K;

@@ -42,6 +42,7 @@ struct SweepArgs {
   DatumP dp;
   uint32_t k0, k1, tag;  // Philox key and tag (FRESH)
   int cv;                // FRESH: also accumulate sum z
+  int mfma;              // 1: contractions on the matrix cores (bf16 table, n >= 16)
   Partials part;
   const int* done;       // Picard stop flag or nullptr
 };
@@ -115,6 +116,10 @@ hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* tabl
 hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G,
                                uint32_t* out, hipStream_t s);
 hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
+
+// Queries per block of the two pair-loop kernels.
+constexpr int kQueriesPerBlockValu = 256;
+constexpr int kQueriesPerBlockMfma = 128;
 
 // Smallest register bucket that holds n dimensions.
 inline int n_bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 48; }

@@ -17,14 +17,21 @@
 #pragma once
 
 #include "kernels.h"
+#include "sweep_mfma.h"
 
 namespace hjg {
 
+// Coordinates that never win a minimum: padded disc pairs and neighbours are
+// centred this far away, so the datum loops need no branch on the runtime
+// pair or neighbour count (1e18^2 stays finite in float32).
+constexpr float kFar = 1e18f;
+
 template <int DATUM, int NM>
 struct PairConst {
-  float u[NM];    // x + theta, the proposal mean
+  float u[NM];    // x + theta, the proposal mean (kFar on padded disc pairs)
   float tl[NM];   // log2(e) theta / sigma (LINEAR: also folds in the datum slope)
   float nb[DATUM == HJG_L_KNN_BALLS ? 3 * kMaxKnn : 1];  // x + theta - neighbour, KNN
+  float sd[DATUM == HJG_L_BALL ? NM : 1];                // sigma on the ball's k coordinates, else 0
   float sg;       // sigma
   float cl;       // log2(e) c
   float a0;       // constant part of a
@@ -54,7 +61,19 @@ __device__ __forceinline__ void pair_setup(PairConst<DATUM, NM>& P, const SweepA
     for (int j = 0; j < kMaxKnn; ++j)
 #pragma unroll
       for (int e = 0; e < 3; ++e)
-        P.nb[3 * j + e] = (j < A.dp.k) ? P.u[e] - A.dp.aux[(int64_t)(3 * j + e) * A.Q + q] : 0.f;
+        P.nb[3 * j + e] = (j < A.dp.k) ? P.u[e] - A.dp.aux[(int64_t)(3 * j + e) * A.Q + q] : kFar;
+  }
+  if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
+#pragma unroll
+    for (int d = 0; d < NM; ++d)
+      if (d >= A.n) P.u[d] = kFar;
+  }
+  if constexpr (DATUM == HJG_L_BALL) {
+#pragma unroll
+    for (int d = 0; d < NM; ++d) {
+      P.sd[d] = d < A.dp.k ? A.sigma : 0.f;
+      if (d >= A.dp.k) P.u[d] = 0.f;
+    }
   }
   if constexpr (DATUM == HJG_L_LINEAR) {
     // l(y) = b + <a, u> + sigma <a, z>: the z-part joins the tilt contraction.
@@ -71,7 +90,9 @@ __device__ __forceinline__ void pair_setup(PairConst<DATUM, NM>& P, const SweepA
 }
 
 // log2 weight of one pair; zf(d) returns the sample's coordinate d (0 beyond n).
-template <int DATUM, int NM, class ZF>
+// MP is the number of disc pairs evaluated (MIN_PAIR_DISKS): the exact count
+// or NM/3 with the padded pairs centred at kFar.
+template <int DATUM, int NM, int MP, class ZF>
 __device__ __forceinline__ float pair_log2w(const PairConst<DATUM, NM>& P, const DatumP& dp, ZF zf) {
   float tz = 0.f;
   float ell = 0.f;
@@ -90,26 +111,22 @@ __device__ __forceinline__ float pair_log2w(const PairConst<DATUM, NM>& P, const
 #pragma unroll
     for (int d = 0; d < NM; ++d) {
       const float z = zf(d);
-      if (d < dp.k) {
-        const float y = fmaf(P.sg, z, P.u[d]);
-        s = fmaf(y, y, s);
-      }
+      const float y = fmaf(P.sd[d], z, P.u[d]);
+      s = fmaf(y, y, s);
       tz = fmaf(z, P.tl[d], tz);
     }
     ell = __builtin_amdgcn_sqrtf(s) - dp.r;
   } else if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
     float best = INFINITY;
 #pragma unroll
-    for (int j = 0; j < NM / 3; ++j) {
-      if (j < dp.m) {
-        const float z0 = zf(3 * j), z1 = zf(3 * j + 1), z2 = zf(3 * j + 2);
-        const float y0 = fmaf(P.sg, z0, P.u[3 * j]);
-        const float y1 = fmaf(P.sg, z1, P.u[3 * j + 1]);
-        best = fminf(best, fmaf(y0, y0, y1 * y1));
-        tz = fmaf(z0, P.tl[3 * j], tz);
-        tz = fmaf(z1, P.tl[3 * j + 1], tz);
-        tz = fmaf(z2, P.tl[3 * j + 2], tz);
-      }
+    for (int j = 0; j < MP; ++j) {
+      const float z0 = zf(3 * j), z1 = zf(3 * j + 1), z2 = zf(3 * j + 2);
+      const float y0 = fmaf(P.sg, z0, P.u[3 * j]);
+      const float y1 = fmaf(P.sg, z1, P.u[3 * j + 1]);
+      best = fminf(best, fmaf(y0, y0, y1 * y1));
+      tz = fmaf(z0, P.tl[3 * j], tz);
+      tz = fmaf(z1, P.tl[3 * j + 1], tz);
+      tz = fmaf(z2, P.tl[3 * j + 2], tz);
     }
     ell = __builtin_amdgcn_sqrtf(best) - dp.r;
   } else if constexpr (DATUM == HJG_L_KNN_BALLS) {
@@ -118,10 +135,8 @@ __device__ __forceinline__ float pair_log2w(const PairConst<DATUM, NM>& P, const
     float best = INFINITY;
 #pragma unroll
     for (int j = 0; j < kMaxKnn; ++j) {
-      if (j < dp.k) {
-        const float e0 = P.nb[3 * j] + s0, e1 = P.nb[3 * j + 1] + s1, e2 = P.nb[3 * j + 2] + s2;
-        best = fminf(best, fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
-      }
+      const float e0 = P.nb[3 * j] + s0, e1 = P.nb[3 * j + 1] + s1, e2 = P.nb[3 * j + 2] + s2;
+      best = fminf(best, fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
     }
 #pragma unroll
     for (int d = 0; d < NM; ++d) tz = fmaf(zf(d), P.tl[d], tz);
@@ -192,7 +207,7 @@ __device__ __forceinline__ void write_partials(const SweepArgs& A, const LseAcc<
 }
 
 // ------------------------------------------------------------ common table (CRN)
-template <int DATUM, int NM, bool BF16>
+template <int DATUM, int NM, int MP, bool BF16>
 __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
   if (A.done && *A.done) return;
   __shared__ float zs[NM][kBlk];
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
 #pragma unroll
       for (int jj = 0; jj < kB; ++jj) {
         const int j = j0 + jj;
-        const float w = pair_log2w<DATUM, NM>(P, A.dp, [&](int d) { return zs[d][j]; });
+        const float w = pair_log2w<DATUM, NM, MP>(P, A.dp, [&](int d) { return zs[d][j]; });
         a[jj] = (j < cnt) ? w : -INFINITY;
       }
       float mb = a[0];
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
 }
 
 // ------------------------------------------------------------------ fresh draws
-template <int DATUM, int NM, bool BF16>
+template <int DATUM, int NM, int MP, bool BF16>
 __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
   if (A.done && *A.done) return;
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
     float a[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
-      const float w = pair_log2w<DATUM, NM>(P, A.dp, [&](int d) { return zr[d][jj]; });
+      const float w = pair_log2w<DATUM, NM, MP>(P, A.dp, [&](int d) { return zr[d][jj]; });
       a[jj] = (i0 + jj < i_end) ? w : -INFINITY;
     }
     const float mb = fmaxf(fmaxf(a[0], a[1]), fmaxf(a[2], a[3]));
@@ -308,34 +323,70 @@ __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
   write_partials<NM>(A, L, q, split, A.cv != 0);
 }
 
-template <int DATUM, int NM>
+template <int DATUM, int NM, int MP>
 hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+  if (a.mfma) {
+    if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
+      if (fresh || !bf16) return hipErrorInvalidValue;
+      const dim3 grid((unsigned)((a.Q + kMQ - 1) / kMQ), (unsigned)a.splits);
+      sweep_mfma_kernel<DATUM, NM, MP><<<grid, 256, 0, s>>>(a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads), (unsigned)a.splits);
   if (fresh) {
     if constexpr (NM <= 16) {
-      if (bf16) sweep_fresh_kernel<DATUM, NM, true><<<grid, kThreads, 0, s>>>(a);
-      else sweep_fresh_kernel<DATUM, NM, false><<<grid, kThreads, 0, s>>>(a);
+      if (bf16) sweep_fresh_kernel<DATUM, NM, MP, true><<<grid, kThreads, 0, s>>>(a);
+      else sweep_fresh_kernel<DATUM, NM, MP, false><<<grid, kThreads, 0, s>>>(a);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
-    if (bf16) sweep_crn_kernel<DATUM, NM, true><<<grid, kThreads, 0, s>>>(a);
-    else sweep_crn_kernel<DATUM, NM, false><<<grid, kThreads, 0, s>>>(a);
+    if (bf16) sweep_crn_kernel<DATUM, NM, MP, true><<<grid, kThreads, 0, s>>>(a);
+    else sweep_crn_kernel<DATUM, NM, MP, false><<<grid, kThreads, 0, s>>>(a);
   }
   return hipGetLastError();
+}
+
+// Disc pairs: the exact pair count as a template argument for the sizes the
+// workloads use, otherwise the bucket's NM/3 pairs with padded pairs far away.
+template <int NM, int M>
+hipError_t launch_pairs_exact(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+  return launch_sweep_dn<HJG_L_MIN_PAIR_DISKS, NM, M>(a, fresh, bf16, s);
 }
 
 template <int DATUM>
 hipError_t launch_sweep_d(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
   if constexpr (DATUM == HJG_L_KNN_BALLS) {
-    return launch_sweep_dn<DATUM, 8>(a, fresh, bf16, s);
+    return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s);
+  } else if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
+    switch (a.n / 3) {
+      case 1: return launch_pairs_exact<4, 1>(a, fresh, bf16, s);
+      case 2: return launch_pairs_exact<8, 2>(a, fresh, bf16, s);
+      case 3: return launch_pairs_exact<16, 3>(a, fresh, bf16, s);
+      case 4: return launch_pairs_exact<16, 4>(a, fresh, bf16, s);
+      case 5: return launch_pairs_exact<16, 5>(a, fresh, bf16, s);
+      case 6: return launch_pairs_exact<32, 6>(a, fresh, bf16, s);
+      case 7: return launch_pairs_exact<32, 7>(a, fresh, bf16, s);
+      case 8: return launch_pairs_exact<32, 8>(a, fresh, bf16, s);
+      case 9: return launch_pairs_exact<32, 9>(a, fresh, bf16, s);
+      case 10: return launch_pairs_exact<32, 10>(a, fresh, bf16, s);
+      case 11: return launch_pairs_exact<48, 11>(a, fresh, bf16, s);
+      case 12: return launch_pairs_exact<48, 12>(a, fresh, bf16, s);
+      case 13: return launch_pairs_exact<48, 13>(a, fresh, bf16, s);
+      case 14: return launch_pairs_exact<48, 14>(a, fresh, bf16, s);
+      case 15: return launch_pairs_exact<48, 15>(a, fresh, bf16, s);
+      default: return launch_pairs_exact<48, 16>(a, fresh, bf16, s);
+    }
   } else {
     switch (n_bucket(a.n)) {
-      case 4: return launch_sweep_dn<DATUM, 4>(a, fresh, bf16, s);
-      case 8: return launch_sweep_dn<DATUM, 8>(a, fresh, bf16, s);
-      case 16: return launch_sweep_dn<DATUM, 16>(a, fresh, bf16, s);
-      case 32: return launch_sweep_dn<DATUM, 32>(a, fresh, bf16, s);
-      default: return launch_sweep_dn<DATUM, 48>(a, fresh, bf16, s);
+      case 4: return launch_sweep_dn<DATUM, 4, 0>(a, fresh, bf16, s);
+      case 8: return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s);
+      case 16: return launch_sweep_dn<DATUM, 16, 0>(a, fresh, bf16, s);
+      case 32: return launch_sweep_dn<DATUM, 32, 0>(a, fresh, bf16, s);
+      default: return launch_sweep_dn<DATUM, 48, 0>(a, fresh, bf16, s);
     }
   }
 }

@@ -78,6 +78,14 @@ CASES = {
     "dubins_n12_fp32": (dict(workloads.C5.problem_fields(), n=12, sample_bf16=False), 700, 2500),
     "dubins_n30_bf16_cv": (dict(workloads.C5.problem_fields(), n=30, grad_cv=True), 400, 1500),
     "zero_ham_small_c": (dict(workloads.C2.problem_fields(), ham="zero", tilt=False, c_min=1e-3), 300, 2000),
+    # matrix-core pair loop (bf16 common table, n >= 16); ragged Q and N
+    "mfma_dubins_n45_ragged": (dict(workloads.C5.problem_fields()), 333, 1000 + 13),
+    "mfma_dubins_n48_notilt": (dict(workloads.C5.problem_fields(), n=48, tilt=False), 260, 777),
+    "mfma_dubins_n18_cv": (dict(workloads.C5.problem_fields(), n=18, grad_cv=True), 500, 2053),
+    "mfma_quad_halfsq_n20": (dict(workloads.C1_QUAD.problem_fields(), n=20, sample_mode="crn_step",
+                                  sample_bf16=True, tilt=True), 300, 1500),
+    "mfma_quad_ball_n16_k3": (dict(workloads.C1.problem_fields(), n=16, datum_p=(3, 1.0), sample_mode="crn_step",
+                                   sample_bf16=True, tilt=True, grad_cv=True), 257, 999),
 }
 
 
@@ -86,7 +94,9 @@ def _run_case(ctx, name, t=None):
     fields, Q, N = CASES[name]
     n = fields["n"]
     w = workloads.C5 if n > 3 else (workloads.C2 if fields["ham"] != "quadratic" else workloads.C1)
-    box = workloads.dubins_box(n // 3) if fields["datum"] == "min_pair_disks" else w.box
+    if fields["ham"] == "quadratic":
+        w = workloads.C1
+    box = workloads.dubins_box(n // 3) if fields["datum"] == "min_pair_disks" else tuple([(-1.0, 1.0)] * n)
     x = workloads.queries(w.resized(n=n, box=box), Q=Q, trial=3).astype(np.float64)
     t = w.t if t is None else t
     pb = oracle_problem(fields)
@@ -116,6 +126,18 @@ def test_value_grad_parity(ctx, name):
     # ESS = S^2/S2 is not invariant to per-sample rounding of the log-weights
     # (|delta a| up to a few u32 |c| L each), unlike v's common-mode part.
     np.testing.assert_allclose(ess, ref.ess, rtol=1e-3)
+
+
+@pytest.mark.parametrize("name", ["mfma_dubins_n45_ragged", "mfma_quad_ball_n16_k3"])
+def test_valu_and_mfma_paths_agree(ctx, name, monkeypatch):
+    a = _run_case(ctx, name)
+    monkeypatch.setenv("HJG_NO_MFMA", "1")
+    b = _run_case(ctx, name)
+    ref, c, theta, sigma, N = a[3], a[4], a[5], a[6], a[7]
+    th = theta if theta is not None else np.zeros_like(a[1])
+    vt = value_tol(ref.v, c, th, sigma, ref.lmax)
+    assert np.all(np.abs(a[0] - b[0]) <= 2 * vt)
+    assert np.all(np.linalg.norm(a[1] - b[1], axis=1) <= 2 * grad_tol(ref.grad, c, sigma, N))
 
 
 def test_value_grad_deterministic(ctx):
