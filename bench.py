@@ -44,6 +44,28 @@ def alu_slots_per_pair(datum: str, n: int) -> int:
     raise ValueError(datum)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "pair_loop_dubins15_n45_mfma.md")
+KERNEL_SOURCES = ["sweep_mfma.h", "sweep_impl.h", "kernels.h", "device.h"]
+
+
+def measured_traffic():
+    """HBM bytes per pair-loop launch from the committed counter profile, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    if not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    mt = re.search(r"traffic-bytes-per-launch:\s*(\d+)", text)
+    mh = re.search(r"source-hash:\s*([0-9a-f]+)", text)
+    if not (mt and mh):
+        return None
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2605_18566_amd", "csrc", name), "rb").read())
+    return int(mt.group(1)) if h.hexdigest()[:16] == mh.group(1) else None
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -78,7 +100,17 @@ def main():
     ap.add_argument("--queries", type=int, default=None, help="override Q (default: the workload's 262,144)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(queries would be split across GPUs with no exchange but a 16-byte residual "
@@ -156,7 +188,7 @@ def main():
                    "draws": "bf16 common table (Philox4x32-10)", "tilt": "Laplace shift from previous iterate",
                    "hamiltonian": w.ham, "datum": w.datum},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK, "traffic": None,
+                     "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                      "kernel": "pair loop (sweep_mfma_kernel<min_pair_disks, 48, 15>)", "kernel_ms_per_launch": per_launch_ms,
                      "launches_timed": launches, "alu_slots_per_pair": slots},
         "cpu_baseline": cpu,
