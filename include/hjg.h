@@ -180,7 +180,9 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
  * when the relative L2 change ||v^(k+1) - v^(k)|| / ||v^(k)|| over the Q states
  * (float64) is below tol (tol <= 0: run all K).  The K iterations are recorded
  * once into a HIP graph and replayed; the stop is a device-side flag.
- *   p0        device [n][Q] warm-start gradient, or NULL for D l(x)
+ *   p0        device [n][Q] warm-start gradient p^(0), or NULL for D l(x)
+ *   v0        device [Q] warm-start value v^(0) (the reference of the first
+ *             residual), or NULL for l(x)
  *   v, grad   device out, [Q] and [n][Q]: the last executed iterate
  *   c_out     device [Q] out: coefficient frozen in the last executed iteration,
  *             or NULL
@@ -196,9 +198,88 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
  */
 int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
                      const float* x, double t, int32_t N, int32_t K, double tol,
-                     uint32_t time_step, const float* p0, float* v, float* grad,
-                     float* c_out, float* ess, uint8_t* flags,
+                     uint32_t time_step, const float* p0, const float* v0,
+                     float* v, float* grad, float* c_out, float* ess, uint8_t* flags,
                      double* resid_hist, int32_t* iters_done, void* hip_stream);
+
+/*
+ * ------------------------------------------------------------------------
+ * Learned surrogate (x, t) -> (v, Dv).
+ *
+ * A multilayer perceptron with n + 1 inputs (state and horizon), `depth`
+ * hidden layers of `width` units with SiLU, and n + 1 linear outputs (value
+ * and gradient), on normalised inputs and outputs.  Forward and backward run
+ * as bfloat16 matrix-core GEMMs with float32 accumulation; float32 master
+ * weights and AdamW moments.  The loss on a batch of B rows, in normalised
+ * output units, is
+ *   (1/B) sum_rows [ (y_0 - T_0)^2 + (grad_weight / n) sum_{j>=1} (y_j - T_j)^2 ].
+ * Trained on values and gradients produced by the Monte-Carlo sweep; used by
+ * hjg_surrogate_sweep as Picard warm start and proposal shift, with the plain
+ * sweep as fallback and judge.  The surrogate lives on the device that was
+ * current when it was created.  Parameter exchange format (host, float32):
+ * for each layer in order, W [out][in] row-major, then b [out].
+ * ------------------------------------------------------------------------
+ */
+typedef struct hjg_surrogate hjg_surrogate;
+
+typedef struct hjg_train_cfg {
+  int32_t epochs;        /* passes over the training rows (>= 1)              */
+  int32_t batch;         /* rows per step, a multiple of 32                    */
+  double lr, lr_min;     /* cosine schedule from lr to lr_min over all steps   */
+  double weight_decay;   /* decoupled (AdamW)                                  */
+  double beta1, beta2, eps;
+  double grad_weight;    /* weight of the gradient outputs in the loss         */
+  uint64_t seed;         /* per-epoch shuffling                                */
+} hjg_train_cfg;
+
+/* Create a network for states of dimension n (1..96); width a multiple of 32
+ * (32..1024); depth 1..16 hidden layers; weights from `seed`; identity
+ * normalisation. */
+int hjg_surrogate_create(hjg_ctx* ctx, int32_t n, int32_t width, int32_t depth,
+                         uint64_t seed, hjg_surrogate** out);
+void hjg_surrogate_destroy(hjg_surrogate* s);
+/* Number of parameters in the exchange format. */
+int hjg_surrogate_param_count(const hjg_surrogate* s, int64_t* count);
+/* Load parameters (host, exchange format) and normalisation (host float32
+ * [4][n+1]: input mean, input std, output mean, output std; std > 0); resets
+ * the optimiser state.  Synchronous. */
+int hjg_surrogate_set_params(hjg_surrogate* s, const float* params, const float* norm);
+/* Copy parameters (and, if norm != NULL, the normalisation) to host memory.
+ * Synchronous. */
+int hjg_surrogate_get_params(const hjg_surrogate* s, float* params, float* norm);
+/* Evaluate at Q states: x device [n][Q], t device [Q]; v device [Q] and grad
+ * device [n][Q] out.  Asynchronous. */
+int hjg_surrogate_predict(hjg_surrogate* s, int64_t Q, const float* x,
+                          const float* t, float* v, float* grad, void* hip_stream);
+/* One forward and backward pass on B rows (B a multiple of 32) with targets
+ * (v device [B], grad device [n][B]): *loss (host) and, if grads != NULL, the
+ * parameter gradient in the exchange format (host).  Synchronous; for
+ * checking the kernels. */
+int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x,
+                            const float* t, const float* v, const float* grad,
+                            double grad_weight, double* loss, float* grads,
+                            void* hip_stream);
+/* Train on M rows (x [n][M], t [M], v [M], grad [n][M], all device); sets the
+ * normalisation from the data; loss_hist (host [epochs], or NULL) receives the
+ * mean training loss of each epoch.  Synchronises the stream each epoch. */
+int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x,
+                        const float* t, const float* v, const float* grad,
+                        const hjg_train_cfg* cfg, double* loss_hist,
+                        void* hip_stream);
+/* Surrogate-accelerated sweep at Q states and horizon t:
+ *   1. (v_S, Dv_S) = surrogate(x, t);
+ *   2. hjg_picard_sweep with N_s draws and K_s iterations from the warm start
+ *      v^(0) = v_S, p^(0) = Dv_S (so the first coefficient and proposal shift
+ *      come from the surrogate), per-state flags with tolerance tol (> 0);
+ *   3. the flagged states are compacted and solved again by the plain sweep
+ *      (no warm start) with N_fb draws and K_fb iterations, and scattered back.
+ * v, grad device out; fell_back device uint8 [Q] out (1 where step 3 ran);
+ * *n_fallback (host) the number of such states.  Synchronises the stream. */
+int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* problem,
+                        int64_t Q, const float* x, double t, int32_t N_s,
+                        int32_t K_s, int32_t N_fb, int32_t K_fb, double tol,
+                        uint32_t time_step, float* v, float* grad,
+                        uint8_t* fell_back, int64_t* n_fallback, void* hip_stream);
 
 /*
  * Kernel timing (profiling hook).  With timing enabled, every launch of the

@@ -1,0 +1,74 @@
+"""FP64 reference of the surrogate network (TEST INFRASTRUCTURE ONLY).
+
+A multilayer perceptron (x, t) -> (v, Dv): input normalisation, `depth`
+hidden layers of width `width` with SiLU, a linear output layer, output
+de-normalisation.  Loss on a batch of B rows, in normalised output units:
+
+    L = (1/B) sum_rows [ (y_0 - T_0)^2 + (lambda/n) sum_{j>=1} (y_j - T_j)^2 ]
+
+Parameters are a list of (W [out][in], b [out]) per layer.  Written from the
+definitions (chain rule by hand); pinned by finite differences in the tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def dsilu(z):
+    s = 1.0 / (1.0 + np.exp(-z))
+    return s * (1.0 + z * (1.0 - s))
+
+
+def init_params(sizes, rng):
+    """He-style uniform init: U(-sqrt(6/fan_in), sqrt(6/fan_in)) * 0.5, zero biases."""
+    params = []
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        lim = 0.5 * np.sqrt(6.0 / fin)
+        params.append((rng.uniform(-lim, lim, (fout, fin)), np.zeros(fout)))
+    return params
+
+
+def forward(params, X):
+    """X [B][in] (normalised).  Returns (Y [B][out], cache)."""
+    acts, pre = [X], []
+    h = X
+    for li, (W, b) in enumerate(params):
+        z = h @ W.T + b
+        pre.append(z)
+        h = silu(z) if li < len(params) - 1 else z
+        acts.append(h)
+    return h, (acts, pre)
+
+
+def loss_and_grads(params, X, T, lam: float):
+    """Loss and its gradient w.r.t. every W and b."""
+    B, nout = T.shape
+    n = nout - 1
+    wts = np.full(nout, lam / n)
+    wts[0] = 1.0
+    Y, (acts, pre) = forward(params, X)
+    diff = Y - T
+    loss = np.sum(wts * diff * diff) / B
+    dY = 2.0 * wts * diff / B
+    grads = [None] * len(params)
+    d = dY
+    for li in range(len(params) - 1, -1, -1):
+        W, _ = params[li]
+        grads[li] = (d.T @ acts[li], d.sum(axis=0))
+        if li > 0:
+            d = (d @ W) * dsilu(pre[li - 1])
+    return loss, grads
+
+
+def normalise(x, mean, std):
+    return (x - mean) / std
+
+
+def predict(params, xt, in_mean, in_std, out_mean, out_std):
+    """Raw (x, t) rows -> raw (v, Dv) rows."""
+    Y, _ = forward(params, normalise(xt, in_mean, in_std))
+    return Y * out_std + out_mean

@@ -40,6 +40,21 @@ class Problem(C.Structure):
     ]
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int32),
+        ("batch", C.c_int32),
+        ("lr", C.c_double),
+        ("lr_min", C.c_double),
+        ("weight_decay", C.c_double),
+        ("beta1", C.c_double),
+        ("beta2", C.c_double),
+        ("eps", C.c_double),
+        ("grad_weight", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
 class HJGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"hjg error {code}: {msg}")
@@ -61,11 +76,27 @@ SIGNATURES = [
     ("hjg_value_grad", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,
                                  C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hjg_surrogate_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                       C.POINTER(C.c_void_p)]),
+    ("hjg_surrogate_destroy", None, [C.c_void_p]),
+    ("hjg_surrogate_param_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("hjg_surrogate_set_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hjg_surrogate_get_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hjg_surrogate_predict", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
+    ("hjg_surrogate_loss_grad", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_double, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    ("hjg_surrogate_train", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(TrainCfg), C.c_void_p, C.c_void_p]),
+    ("hjg_surrogate_sweep", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p,
+                                      C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                      C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
+                                      C.c_void_p]),
     ("hjg_set_timing", C.c_int, [C.c_void_p, C.c_int32]),
     ("hjg_sweep_time", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("hjg_picard_sweep", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,
                                    C.c_int32, C.c_double, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int32), C.c_void_p]),
 ]
 

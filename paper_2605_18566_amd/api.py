@@ -169,8 +169,8 @@ class PicardOut:
 
 
 def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, K: int, tol: float = 0.0,
-                 time_step: int = 0, p0: Optional[torch.Tensor] = None, host_outputs: bool = True,
-                 out: Optional[PicardOut] = None, stream=None) -> PicardOut:
+                 time_step: int = 0, p0: Optional[torch.Tensor] = None, v0: Optional[torch.Tensor] = None,
+                 host_outputs: bool = True, out: Optional[PicardOut] = None, stream=None) -> PicardOut:
     """Algorithm 1 at the states x [n][Q]; see hjg_picard_sweep."""
     _require_cuda(x, "x")
     n, Q = x.shape
@@ -178,6 +178,8 @@ def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: 
         raise ValueError("x must have shape [n, Q]")
     if p0 is not None:
         _require_cuda(p0, "p0")
+    if v0 is not None:
+        _require_cuda(v0, "v0")
     dev = x.device
     if out is None:
         out = PicardOut(torch.empty(Q, dtype=torch.float32, device=dev),
@@ -190,7 +192,7 @@ def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: 
     iters = C.c_int32(0)
     p = spec.to_c()
     code = _lib.lib().hjg_picard_sweep(ctx.handle, C.byref(p), Q, _ptr(x), float(t), int(N), int(K), float(tol),
-                                       int(time_step), _ptr(p0), _ptr(out.v), _ptr(out.grad), _ptr(out.c),
+                                       int(time_step), _ptr(p0), _ptr(v0), _ptr(out.v), _ptr(out.grad), _ptr(out.c),
                                        _ptr(out.ess), _ptr(out.flags), hist,
                                        C.byref(iters) if host_outputs else None, _stream(stream))
     check(code, allow=(_lib.HJG_OK, _lib.HJG_ENOTCONVERGED))
@@ -199,3 +201,119 @@ def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: 
         out.resid_hist = np.array(list(hist))
         out.iters_done = int(iters.value)
     return out
+
+
+# ----------------------------------------------------------------- surrogate
+@dataclass
+class TrainConfig:
+    """Training settings (struct hjg_train_cfg)."""
+    epochs: int = 20
+    batch: int = 4096
+    lr: float = 1e-3
+    lr_min: float = 1e-5
+    weight_decay: float = 1e-4
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    grad_weight: float = 1.0
+    seed: int = 0
+
+    def to_c(self) -> _lib.TrainCfg:
+        c = _lib.TrainCfg()
+        c.epochs, c.batch = int(self.epochs), int(self.batch)
+        c.lr, c.lr_min, c.weight_decay = float(self.lr), float(self.lr_min), float(self.weight_decay)
+        c.beta1, c.beta2, c.eps = float(self.beta1), float(self.beta2), float(self.eps)
+        c.grad_weight, c.seed = float(self.grad_weight), int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        return c
+
+
+def _host_f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+class Surrogate:
+    """The library's surrogate network (x, t) -> (v, Dv) on the context's device."""
+
+    def __init__(self, ctx: Context, n: int, width: int = 256, depth: int = 4, seed: int = 0):
+        h = C.c_void_p()
+        check(_lib.lib().hjg_surrogate_create(ctx.handle, int(n), int(width), int(depth),
+                                              int(seed) & 0xFFFFFFFFFFFFFFFF, C.byref(h)))
+        self._h, self.n, self.width, self.depth, self.ctx = h, n, width, depth, ctx
+
+    @property
+    def handle(self):
+        return self._h
+
+    def param_count(self) -> int:
+        c = C.c_int64(0)
+        check(_lib.lib().hjg_surrogate_param_count(self._h, C.byref(c)))
+        return int(c.value)
+
+    def set_params(self, params, norm):
+        p, nm = _host_f32(params), _host_f32(norm)
+        if p.size != self.param_count() or nm.shape != (4, self.n + 1):
+            raise ValueError("params or norm has the wrong size")
+        check(_lib.lib().hjg_surrogate_set_params(self._h, p.ctypes.data, nm.ctypes.data))
+
+    def get_params(self):
+        p = np.zeros(self.param_count(), dtype=np.float32)
+        nm = np.zeros((4, self.n + 1), dtype=np.float32)
+        check(_lib.lib().hjg_surrogate_get_params(self._h, p.ctypes.data, nm.ctypes.data))
+        return p, nm
+
+    def predict(self, x: torch.Tensor, t, stream=None):
+        _require_cuda(x, "x")
+        n, Q = x.shape
+        tq = t if isinstance(t, torch.Tensor) else torch.full((Q,), float(t), dtype=torch.float32, device=x.device)
+        _require_cuda(tq, "t")
+        v = torch.empty(Q, dtype=torch.float32, device=x.device)
+        g = torch.empty((n, Q), dtype=torch.float32, device=x.device)
+        check(_lib.lib().hjg_surrogate_predict(self._h, Q, _ptr(x), _ptr(tq), _ptr(v), _ptr(g), _stream(stream)))
+        return v, g
+
+    def loss_grad(self, x, t, v, grad, grad_weight: float = 1.0, stream=None):
+        for name, a in (("x", x), ("t", t), ("v", v), ("grad", grad)):
+            _require_cuda(a, name)
+        B = x.shape[1]
+        loss = C.c_double(0.0)
+        g = np.zeros(self.param_count(), dtype=np.float32)
+        check(_lib.lib().hjg_surrogate_loss_grad(self._h, B, _ptr(x), _ptr(t), _ptr(v), _ptr(grad),
+                                                 float(grad_weight), C.byref(loss), g.ctypes.data, _stream(stream)))
+        return loss.value, g
+
+    def train(self, x, t, v, grad, cfg: TrainConfig = TrainConfig(), stream=None) -> np.ndarray:
+        for name, a in (("x", x), ("t", t), ("v", v), ("grad", grad)):
+            _require_cuda(a, name)
+        M = x.shape[1]
+        hist = np.zeros(cfg.epochs, dtype=np.float64)
+        c = cfg.to_c()
+        check(_lib.lib().hjg_surrogate_train(self._h, M, _ptr(x), _ptr(t), _ptr(v), _ptr(grad), C.byref(c),
+                                             hist.ctypes.data, _stream(stream)))
+        return hist
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().hjg_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def surrogate_sweep(ctx: Context, sur: Surrogate, spec: ProblemSpec, x: torch.Tensor, t: float, N_s: int, K_s: int,
+                    N_fb: int, K_fb: int, tol: float = 1e-3, time_step: int = 0, stream=None):
+    """Surrogate-accelerated sweep; returns (v, grad, fell_back, n_fallback)."""
+    _require_cuda(x, "x")
+    n, Q = x.shape
+    v = torch.empty(Q, dtype=torch.float32, device=x.device)
+    g = torch.empty((n, Q), dtype=torch.float32, device=x.device)
+    fb = torch.empty(Q, dtype=torch.uint8, device=x.device)
+    nfb = C.c_int64(0)
+    p = spec.to_c()
+    check(_lib.lib().hjg_surrogate_sweep(ctx.handle, sur.handle, C.byref(p), Q, _ptr(x), float(t), int(N_s),
+                                         int(K_s), int(N_fb), int(K_fb), float(tol), int(time_step), _ptr(v),
+                                         _ptr(g), _ptr(fb), C.byref(nfb), _stream(stream)))
+    return v, g, fb, int(nfb.value)

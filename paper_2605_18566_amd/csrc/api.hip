@@ -286,6 +286,12 @@ int check_common(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, double t, int32_
 
 extern "C" {
 
+// Error reporting shared with the other translation units of the library.
+__attribute__((visibility("hidden"))) int hjg_internal_fail(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
 const char* hjg_last_error(void) { return g_err.c_str(); }
 
 const char* hjg_version(void) { return "hjg 0.1 (gfx950)"; }
@@ -438,7 +444,7 @@ struct PicardKey {
   int32_t N, K;
   double tol;
   uint32_t step;
-  const float *p0;
+  const float *p0, *v0;
   float *v, *grad, *c_out, *ess;
   uint8_t* flags;
   void* table;
@@ -487,6 +493,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
   in.sigma = sigma;
   in.x = k.x;
   in.p0 = k.p0;
+  in.v0 = k.v0;
   in.dp = datum_params(p);
   in.hp = ham_params(p);
   in.tilt = p->tilt;
@@ -569,8 +576,9 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
 }  // namespace
 
 int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N, int32_t K,
-                     double tol, uint32_t step, const float* p0, float* v, float* grad, float* c_out, float* ess,
-                     uint8_t* flags, double* resid_hist, int32_t* iters_done, void* hip_stream) {
+                     double tol, uint32_t step, const float* p0, const float* v0, float* v, float* grad,
+                     float* c_out, float* ess, uint8_t* flags, double* resid_hist, int32_t* iters_done,
+                     void* hip_stream) {
   g_err.clear();
   int rc = check_common(ctx, p, Q, t, N, step);
   if (rc) return rc;
@@ -606,6 +614,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   key.tol = tol;
   key.step = step;
   key.p0 = p0;
+  key.v0 = v0;
   key.v = v;
   key.grad = grad;
   key.c_out = c_out;

@@ -83,7 +83,8 @@ struct InitArgs {
   int K;
   float sigma;
   const float* x;
-  const float* p0;       // warm start or nullptr
+  const float* p0;       // warm-start gradient or nullptr
+  const float* v0;       // warm-start value or nullptr (then v^(0) = l(x))
   DatumP dp;
   HamP hp;
   int tilt;

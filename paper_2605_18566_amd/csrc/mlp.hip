@@ -1,0 +1,432 @@
+// Surrogate-network kernels: bfloat16 matrix-core GEMM with fused epilogues,
+// loss, bias gradients, AdamW, data preparation, and the compaction used by
+// the surrogate-accelerated sweep's fallback.
+#include <algorithm>
+
+#include "mlp.h"
+
+namespace hjg {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kTM = 64, kTN = 64, kTK = 32;   // block tile
+constexpr int kLdsK = kTK + 8;                 // padded LDS row (80 bytes, 16-byte aligned)
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Block tile 64 x 64, 4 waves as 2 x 2 sub-tiles of 32 x 32, each sub-tile one
+// v_mfma_f32_32x32x16_bf16 chain (two per 32-deep K slice).  Operand lanes:
+// A[i = l%32][k = 8(l/32)..+7], B[k = 8(l/32)..+7][j = l%32]; accumulator
+// lane l holds rows 8(v/4) + 4(l/32) + v%4 of column l%32.
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[kTM][kLdsK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[kTN][kLdsK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  int kb = 0, ke = g.K;
+  if (EPI == EPI_DW) {
+    kb = blockIdx.z * g.k_per_split;
+    ke = min(g.K, kb + g.k_per_split);
+  }
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row, k offset
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
+    bf16x8 va, vb;
+    if (m0 + lr < g.M) va = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr) * g.lda + k0 + lk);
+    else
+#pragma unroll
+      for (int e = 0; e < 8; ++e) va[e] = (__bf16)0.f;
+    if (n0 + lr < g.N) vb = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)(n0 + lr) * g.ldb + k0 + lk);
+    else
+#pragma unroll
+      for (int e = 0; e < 8; ++e) vb[e] = (__bf16)0.f;
+    *reinterpret_cast<bf16x8*>(&As[lr][lk]) = va;
+    *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = vb;
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kTK; ks += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int n = n0 + wn * 32 + (lane & 31);
+  if (n >= g.N) return;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+    if (m >= g.M) continue;
+    const float c = acc[v];
+    if (EPI == EPI_FWD_HIDDEN) {
+      const float z = c + g.bias[n];
+      if (g.outf) g.outf[(int64_t)m * g.ldo + n] = z;
+      const __bf16 s = (__bf16)(z * sigmoidf_(z));
+      if (g.outb) g.outb[(int64_t)m * g.ldob + n] = s;
+      if (g.outbT) g.outbT[(int64_t)n * g.ldobT + m] = s;
+    } else if (EPI == EPI_FWD_OUT) {
+      g.outf[(int64_t)m * g.ldo + n] = c + g.bias[n];
+    } else if (EPI == EPI_BWD_DX) {
+      const float z = g.zprev[(int64_t)m * g.ldz + n];
+      const float sg = sigmoidf_(z);
+      const __bf16 d = (__bf16)(c * sg * (1.0f + z * (1.0f - sg)));
+      g.outb[(int64_t)m * g.ldob + n] = d;
+      g.outbT[(int64_t)n * g.ldobT + m] = d;
+    } else {
+      g.outf[((int64_t)blockIdx.z * g.M + m) * g.ldo + n] = c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_splits_kernel(const float* part, int splits, int M, int N, int ld,
+                                                         float* dst, int ldd) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[((int64_t)z * M + m) * ld + n];
+  dst[(int64_t)m * ldd + n] = s;
+}
+
+__global__ __launch_bounds__(256) void row_sums_kernel(const __bf16* inT, int C, int ld, float* out) {
+  const int r = blockIdx.x;
+  float s = 0.f;
+  for (int c = threadIdx.x; c < C; c += 256) s += (float)inT[(int64_t)r * ld + c];
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = red[0];
+}
+
+__global__ __launch_bounds__(256) void mse_kernel(const float* Y, const float* T, const float* w, int B, int cols,
+                                                  int ld, __bf16* dY, __bf16* dYT, double* block_loss) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (i < (int64_t)B * ld) {
+    const int r = (int)(i / ld), c = (int)(i % ld);
+    float d = 0.f;
+    if (c < cols) {
+      const float diff = Y[i] - T[i];
+      l = (double)w[c] * (double)diff * (double)diff;
+      d = 2.0f * w[c] * diff / (float)B;
+    }
+    dY[i] = (__bf16)d;
+    dYT[(int64_t)c * B + r] = (__bf16)d;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_loss[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void adamw_kernel(float* w, const float* g, float* m, float* v, int64_t count,
+                                                    float lr, float b1, float b2, float eps, float wd, float bc1,
+                                                    float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / bc1, vh = vi / bc2;
+  w[i] = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* W, int rows, int cols, __bf16* Wb, __bf16* WbT) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  const __bf16 b = (__bf16)W[i];
+  Wb[i] = b;
+  WbT[(int64_t)c * rows + r] = b;
+}
+
+__global__ __launch_bounds__(256) void prep_inputs_kernel(const float* x, int64_t xstride, const float* t, int n,
+                                                          int64_t rows, int ld, const float* mean, const float* stdv,
+                                                          __bf16* X, __bf16* XT) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * ld) return;
+  const int64_t r = i / ld;
+  const int c = (int)(i % ld);
+  float val = 0.f;
+  if (c < n) val = (x[(int64_t)c * xstride + r] - mean[c]) / stdv[c];
+  else if (c == n) val = (t[r] - mean[n]) / stdv[n];
+  const __bf16 b = (__bf16)val;
+  X[i] = b;
+  if (XT) XT[(int64_t)c * rows + r] = b;
+}
+
+__global__ __launch_bounds__(256) void prep_targets_kernel(const float* v, const float* grad, int n, int64_t rows,
+                                                           int ld, const float* mean, const float* stdv, float* T) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * ld) return;
+  const int64_t r = i / ld;
+  const int c = (int)(i % ld);
+  float val = 0.f;
+  if (c == 0) val = (v[r] - mean[0]) / stdv[0];
+  else if (c <= n) val = (grad[(int64_t)(c - 1) * rows + r] - mean[c]) / stdv[c];
+  T[i] = val;
+}
+
+__global__ __launch_bounds__(256) void post_outputs_kernel(const float* Y, int n, int64_t rows, int ld,
+                                                           const float* mean, const float* stdv, float* v,
+                                                           float* grad, int64_t gstride) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  v[r] = Y[r * ld] * stdv[0] + mean[0];
+  for (int d = 0; d < n; ++d) grad[(int64_t)d * gstride + r] = Y[r * ld + 1 + d] * stdv[1 + d] + mean[1 + d];
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* p, float val, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = val;
+}
+
+// acc[0] += sum of the block partials (fixed order)
+__global__ __launch_bounds__(256) void accumulate_kernel(const double* part, int count, double* acc) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) s += part[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += red[0];
+}
+
+__global__ __launch_bounds__(256) void feature_stats_kernel(const float* base, int64_t stride, int64_t rows,
+                                                            float* mean, float* stdv) {
+  const int f = blockIdx.x;
+  const float* src = base + f * stride;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) {
+    const double x = src[r];
+    s += x;
+    s2 += x * x;
+  }
+  __shared__ double a[256], b[256];
+  a[threadIdx.x] = s;
+  b[threadIdx.x] = s2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) { a[threadIdx.x] += a[threadIdx.x + off]; b[threadIdx.x] += b[threadIdx.x + off]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mu = a[0] / (double)rows;
+    const double var = fmax(b[0] / (double)rows - mu * mu, 0.0);
+    const double sd = sqrt(var);
+    mean[f] = (float)mu;
+    stdv[f] = sd > 1e-6 ? (float)sd : 1.0f;   // a constant feature is left unscaled
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const __bf16* X_all, const float* T_all, const int* perm, int B,
+                                                     int ld, int ldt, __bf16* Xb, __bf16* XbT, float* Tb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < (int64_t)B * ld) {
+    const int r = (int)(i / ld), c = (int)(i % ld);
+    const __bf16 x = X_all[(int64_t)perm[r] * ld + c];
+    Xb[i] = x;
+    XbT[(int64_t)c * B + r] = x;
+  }
+  if (i < (int64_t)B * ldt) {
+    const int r = (int)(i / ldt), c = (int)(i % ldt);
+    Tb[i] = T_all[(int64_t)perm[r] * ldt + c];
+  }
+}
+
+__global__ __launch_bounds__(256) void compact_count_kernel(const uint8_t* flags, int64_t Q, int* block_counts) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int f = (q < Q && flags[q]) ? 1 : 0;
+  const int c = __syncthreads_count(f);
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = c;
+}
+
+// exclusive scan of the block counts in place (one thread; at most a few
+// thousand blocks); total written separately
+__global__ void compact_scan_kernel(int* counts, int nblocks, int* total) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int run = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    const int c = counts[b];
+    counts[b] = run;
+    run += c;
+  }
+  *total = run;
+}
+
+__global__ __launch_bounds__(256) void compact_write_kernel(const uint8_t* flags, int64_t Q, const int* offsets,
+                                                            int* index) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int f = (q < Q && flags[q]) ? 1 : 0;
+  __shared__ int pre[256];
+  pre[threadIdx.x] = f;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {     // inclusive Hillis-Steele scan
+    const int add = (int)threadIdx.x >= off ? pre[threadIdx.x - off] : 0;
+    __syncthreads();
+    pre[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (f) index[offsets[blockIdx.x] + pre[threadIdx.x] - 1] = (int)q;
+}
+
+__global__ __launch_bounds__(256) void gather_soa_kernel(const float* src, int n, int64_t Q, const int* index,
+                                                         int64_t count, float* dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count * n) return;
+  const int d = (int)(i / count);
+  const int64_t j = i % count;
+  dst[(int64_t)d * count + j] = src[(int64_t)d * Q + index[j]];
+}
+
+__global__ __launch_bounds__(256) void scatter_soa_kernel(const float* src, int n, int64_t count, const int* index,
+                                                          int64_t Q, float* dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count * n) return;
+  const int d = (int)(i / count);
+  const int64_t j = i % count;
+  dst[(int64_t)d * Q + index[j]] = src[(int64_t)d * count + j];
+}
+
+unsigned nblk(int64_t work) { return (unsigned)std::max<int64_t>((work + 255) / 256, 1); }
+
+}  // namespace
+
+hipError_t launch_gemm(int epi, const GemmArgs& a, int splits, hipStream_t s) {
+  if (a.K % kTK) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.N + kTN - 1) / kTN), (unsigned)((a.M + kTM - 1) / kTM),
+                  (unsigned)(epi == EPI_DW ? splits : 1));
+  switch (epi) {
+    case EPI_FWD_HIDDEN: gemm_nt_kernel<EPI_FWD_HIDDEN><<<grid, 256, 0, s>>>(a); break;
+    case EPI_FWD_OUT: gemm_nt_kernel<EPI_FWD_OUT><<<grid, 256, 0, s>>>(a); break;
+    case EPI_BWD_DX: gemm_nt_kernel<EPI_BWD_DX><<<grid, 256, 0, s>>>(a); break;
+    case EPI_DW: gemm_nt_kernel<EPI_DW><<<grid, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_splits(const float* part, int splits, int M, int N, int ld, float* dst, int ldd,
+                             hipStream_t s) {
+  sum_splits_kernel<<<nblk((int64_t)M * N), 256, 0, s>>>(part, splits, M, N, ld, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sums(const __bf16* inT, int R, int C, int ld, float* out, hipStream_t s) {
+  row_sums_kernel<<<R, 256, 0, s>>>(inT, C, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse_loss(const float* Y, const float* T, const float* w, int B, int cols, int ld, __bf16* dY,
+                           __bf16* dYT, double* block_loss, int* nblocks, hipStream_t s) {
+  const unsigned nb = nblk((int64_t)B * ld);
+  *nblocks = (int)nb;
+  mse_kernel<<<nb, 256, 0, s>>>(Y, T, w, B, cols, ld, dY, dYT, block_loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int64_t count, float lr, float beta1,
+                        float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s) {
+  adamw_kernel<<<nblk(count), 256, 0, s>>>(w, g, m, v, count, lr, beta1, beta2, eps, wd, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* WbT, hipStream_t s) {
+  to_bf16_kernel<<<nblk((int64_t)rows * cols), 256, 0, s>>>(W, rows, cols, Wb, WbT);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_inputs(const float* x, int64_t xstride, const float* t, int n, int64_t rows, int ld,
+                              const float* mean, const float* stdv, __bf16* X, __bf16* XT, hipStream_t s) {
+  prep_inputs_kernel<<<nblk(rows * ld), 256, 0, s>>>(x, xstride, t, n, rows, ld, mean, stdv, X, XT);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_targets(const float* v, const float* grad, int n, int64_t rows, int ld, const float* mean,
+                               const float* stdv, float* T, hipStream_t s) {
+  prep_targets_kernel<<<nblk(rows * ld), 256, 0, s>>>(v, grad, n, rows, ld, mean, stdv, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_post_outputs(const float* Y, int n, int64_t rows, int ld, const float* mean, const float* stdv,
+                               float* v, float* grad, int64_t gstride, hipStream_t s) {
+  post_outputs_kernel<<<nblk(rows), 256, 0, s>>>(Y, n, rows, ld, mean, stdv, v, grad, gstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, float val, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  fill_kernel<<<nblk(count), 256, 0, s>>>(p, val, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const double* part, int count, double* acc, hipStream_t s) {
+  accumulate_kernel<<<1, 256, 0, s>>>(part, count, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_feature_stats(const float* base, int64_t stride, int nf, int64_t rows, float* mean, float* stdv,
+                                hipStream_t s) {
+  feature_stats_kernel<<<nf, 256, 0, s>>>(base, stride, rows, mean, stdv);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const __bf16* X_all, const float* T_all, const int* perm, int B, int ld, int ldt,
+                         __bf16* Xb, __bf16* XbT, float* Tb, hipStream_t s) {
+  gather_kernel<<<nblk((int64_t)B * std::max(ld, ldt)), 256, 0, s>>>(X_all, T_all, perm, B, ld, ldt, Xb, XbT, Tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_count(const uint8_t* flags, int64_t Q, int* block_counts, int* nblocks, hipStream_t s) {
+  const unsigned nb = nblk(Q);
+  *nblocks = (int)nb;
+  compact_count_kernel<<<nb, 256, 0, s>>>(flags, Q, block_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_scan(int* block_counts, int nblocks, int* total, hipStream_t s) {
+  compact_scan_kernel<<<1, 64, 0, s>>>(block_counts, nblocks, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_write(const uint8_t* flags, int64_t Q, const int* block_offsets, int* index,
+                                hipStream_t s) {
+  compact_write_kernel<<<nblk(Q), 256, 0, s>>>(flags, Q, block_offsets, index);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_soa(const float* src, int n, int64_t Q, const int* index, int64_t count, float* dst,
+                             hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  gather_soa_kernel<<<nblk(count * n), 256, 0, s>>>(src, n, Q, index, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_soa(const float* src, int n, int64_t count, const int* index, int64_t Q, float* dst,
+                              hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  scatter_soa_kernel<<<nblk(count * n), 256, 0, s>>>(src, n, count, index, Q, dst);
+  return hipGetLastError();
+}
+
+}  // namespace hjg

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) {
 #pragma unroll
   for (int d = 0; d < NM; ++d) x[d] = d < I.n ? I.x[(int64_t)d * I.Q + q] : 0.f;
   const float l = datum_and_grad<NM>(I.dp, x, g, q, I.Q);
-  I.vprev[q] = l;                                   // v^(0) = l(x)
+  I.vprev[q] = I.v0 ? I.v0[q] : l;                  // v^(0) = l(x), or the warm start
   if (I.p0) {
 #pragma unroll
     for (int d = 0; d < NM; ++d) g[d] = d < I.n ? I.p0[(int64_t)d * I.Q + q] : 0.f;

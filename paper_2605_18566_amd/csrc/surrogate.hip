@@ -1,0 +1,565 @@
+// Surrogate network (x, t) -> (v, Dv): parameters, forward and backward on the
+// matrix cores, AdamW training with a native data loader (per-epoch
+// permutation), prediction, and the surrogate-accelerated sweep with
+// plain Monte-Carlo fallback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hjg.h"
+#include "mlp.h"
+
+using namespace hjg;
+
+// Defined in api.hip: per-thread error message.
+extern "C" __attribute__((visibility("hidden"))) int hjg_internal_fail(int code, const char* msg);
+
+namespace {
+
+int fail(int code, const std::string& msg) { return hjg_internal_fail(code, msg.c_str()); }
+
+#define SG_HIP(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(HJG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int round32(int v) { return (v + 31) / 32 * 32; }
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+int grow(Buf& b, size_t bytes) {
+  if (bytes <= b.bytes) return HJG_OK;
+  SG_HIP(hipDeviceSynchronize());
+  if (b.p) SG_HIP(hipFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  if (hipMalloc(&b.p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HJG_ENOMEM, "surrogate workspace allocation failed");
+  }
+  b.bytes = std::max<size_t>(bytes, 256);
+  return HJG_OK;
+}
+
+// splitmix64: seeds the host-side permutation and the initial weights
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double uniform01(uint64_t& s) { return (double)(splitmix64(s) >> 11) * 0x1.0p-53; }
+
+}  // namespace
+
+struct hjg_surrogate {
+  hjg_ctx* ctx = nullptr;
+  int device = 0;
+  int n = 0, width = 0, depth = 0;
+  int nin = 0, nout = 0, in_p = 0, out_p = 0;
+  int L = 0;                        // layers = depth + 1
+  std::vector<int> fin, fout;       // padded fan-in / fan-out per layer
+  std::vector<int> tin, tout;       // true fan-in / fan-out per layer
+  std::vector<int64_t> woff, boff;  // offsets into the padded flat buffers
+  int64_t P = 0;                    // padded parameter count
+  Buf w, g, m, v;                   // float32 master weights, gradients, Adam moments
+  std::vector<Buf> Wb, WbT;         // bfloat16 copies per layer
+  Buf norm;                         // float32 [4][nin]: in mean, in std, out mean, out std
+  Buf lw;                           // loss weights [out_p]
+  int64_t step = 0;
+  // batch workspace
+  int64_t cap = 0;
+  Buf X0, X0T, Y, T, dY, dYT, part, bl, acc, perm;
+  std::vector<Buf> Z, X, XT;
+  Buf dZ[2], dZT[2];
+  // training set and sweep workspace
+  Buf Xall, Tall, sv, sg, tq, flags, bcount, total, index, xfb, vfb, gfb;
+};
+
+namespace {
+
+int ensure_batch(hjg_surrogate* s, int64_t rows, bool train) {
+  int rc;
+  if (rows <= s->cap && (!train || s->dY.bytes >= (size_t)rows * s->out_p * 2)) return HJG_OK;
+  const int64_t r = std::max<int64_t>(rows, s->cap);
+  if ((rc = grow(s->X0, r * s->in_p * 2))) return rc;
+  if ((rc = grow(s->Y, r * s->out_p * 4))) return rc;
+  s->Z.resize(s->depth);
+  s->X.resize(s->depth);
+  s->XT.resize(s->depth);
+  for (int l = 0; l < s->depth; ++l)
+    if ((rc = grow(s->X[l], r * s->width * 2))) return rc;
+  if (train) {
+    if ((rc = grow(s->X0T, r * s->in_p * 2))) return rc;
+    if ((rc = grow(s->T, r * s->out_p * 4))) return rc;
+    if ((rc = grow(s->dY, r * s->out_p * 2))) return rc;
+    if ((rc = grow(s->dYT, r * s->out_p * 2))) return rc;
+    for (int l = 0; l < s->depth; ++l) {
+      if ((rc = grow(s->Z[l], r * s->width * 4))) return rc;
+      if ((rc = grow(s->XT[l], r * s->width * 2))) return rc;
+    }
+    for (int i = 0; i < 2; ++i) {
+      if ((rc = grow(s->dZ[i], r * s->width * 2))) return rc;
+      if ((rc = grow(s->dZT[i], r * s->width * 2))) return rc;
+    }
+    if ((rc = grow(s->bl, (r * s->out_p / 256 + 2) * 8))) return rc;
+    if ((rc = grow(s->acc, 64))) return rc;
+  }
+  s->cap = r;
+  return HJG_OK;
+}
+
+int refresh_bf16(hjg_surrogate* s, hipStream_t st) {
+  for (int l = 0; l < s->L; ++l)
+    SG_HIP(launch_to_bf16((const float*)s->w.p + s->woff[l], s->fout[l], s->fin[l], (__bf16*)s->Wb[l].p,
+                          (__bf16*)s->WbT[l].p, st));
+  return HJG_OK;
+}
+
+const float* nrm(const hjg_surrogate* s, int which) { return (const float*)s->norm.p + which * s->nin; }
+
+// Forward pass over `rows` rows of X0.  With `train`, also keeps the
+// pre-activations and the transposed activations for the backward pass.
+int forward(hjg_surrogate* s, int64_t rows, bool train, hipStream_t st) {
+  const __bf16* h = (const __bf16*)s->X0.p;
+  int ldh = s->in_p;
+  for (int l = 0; l < s->depth; ++l) {
+    GemmArgs a{};
+    a.A = h;
+    a.lda = ldh;
+    a.B = (const __bf16*)s->Wb[l].p;
+    a.ldb = s->fin[l];
+    a.M = (int)rows;
+    a.N = s->fout[l];
+    a.K = s->fin[l];
+    a.bias = (const float*)s->w.p + s->boff[l];
+    a.outf = train ? (float*)s->Z[l].p : nullptr;
+    a.ldo = s->width;
+    a.outb = (__bf16*)s->X[l].p;
+    a.ldob = s->width;
+    a.outbT = train ? (__bf16*)s->XT[l].p : nullptr;
+    a.ldobT = (int)rows;
+    SG_HIP(launch_gemm(EPI_FWD_HIDDEN, a, 1, st));
+    h = (const __bf16*)s->X[l].p;
+    ldh = s->width;
+  }
+  GemmArgs a{};
+  a.A = h;
+  a.lda = ldh;
+  a.B = (const __bf16*)s->Wb[s->depth].p;
+  a.ldb = s->width;
+  a.M = (int)rows;
+  a.N = s->out_p;
+  a.K = s->width;
+  a.bias = (const float*)s->w.p + s->boff[s->depth];
+  a.outf = (float*)s->Y.p;
+  a.ldo = s->out_p;
+  SG_HIP(launch_gemm(EPI_FWD_OUT, a, 1, st));
+  return HJG_OK;
+}
+
+// Loss (added to s->acc[0]) and gradients of all parameters into s->g for a
+// batch already forwarded with train = true, targets in s->T.
+int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
+  int rc;
+  const int B = (int)rows;
+  int nb = 0;
+  SG_HIP(launch_mse_loss((const float*)s->Y.p, (const float*)s->T.p, (const float*)s->lw.p, B, s->nout, s->out_p,
+                         (__bf16*)s->dY.p, (__bf16*)s->dYT.p, (double*)s->bl.p, &nb, st));
+  SG_HIP(launch_accumulate((const double*)s->bl.p, nb, (double*)s->acc.p, st));
+  const int kps = 512;
+  const int splits = (B + kps - 1) / kps;
+  if ((rc = grow(s->part, (size_t)splits * s->width * std::max(s->width, s->in_p) * 4 +
+                              (size_t)splits * s->out_p * s->width * 4)))
+    return rc;
+  float* g = (float*)s->g.p;
+  // output layer
+  {
+    const int l = s->depth;
+    GemmArgs a{};
+    a.A = (const __bf16*)s->dYT.p;
+    a.lda = B;
+    a.B = (const __bf16*)s->XT[l - 1].p;
+    a.ldb = B;
+    a.M = s->out_p;
+    a.N = s->width;
+    a.K = B;
+    a.k_per_split = kps;
+    a.outf = (float*)s->part.p;
+    a.ldo = s->width;
+    SG_HIP(launch_gemm(EPI_DW, a, splits, st));
+    SG_HIP(launch_sum_splits((const float*)s->part.p, splits, s->out_p, s->width, s->width, g + s->woff[l], s->width,
+                             st));
+    SG_HIP(launch_row_sums((const __bf16*)s->dYT.p, s->out_p, B, B, g + s->boff[l], st));
+    GemmArgs d{};
+    d.A = (const __bf16*)s->dY.p;
+    d.lda = s->out_p;
+    d.B = (const __bf16*)s->WbT[l].p;
+    d.ldb = s->out_p;
+    d.M = B;
+    d.N = s->width;
+    d.K = s->out_p;
+    d.outb = (__bf16*)s->dZ[0].p;
+    d.ldob = s->width;
+    d.outbT = (__bf16*)s->dZT[0].p;
+    d.ldobT = B;
+    d.zprev = (const float*)s->Z[l - 1].p;
+    d.ldz = s->width;
+    SG_HIP(launch_gemm(EPI_BWD_DX, d, 1, st));
+  }
+  int cur = 0;
+  for (int l = s->depth - 1; l >= 0; --l) {
+    const __bf16* inT = l == 0 ? (const __bf16*)s->X0T.p : (const __bf16*)s->XT[l - 1].p;
+    GemmArgs a{};
+    a.A = (const __bf16*)s->dZT[cur].p;
+    a.lda = B;
+    a.B = inT;
+    a.ldb = B;
+    a.M = s->width;
+    a.N = s->fin[l];
+    a.K = B;
+    a.k_per_split = kps;
+    a.outf = (float*)s->part.p;
+    a.ldo = s->fin[l];
+    SG_HIP(launch_gemm(EPI_DW, a, splits, st));
+    SG_HIP(launch_sum_splits((const float*)s->part.p, splits, s->width, s->fin[l], s->fin[l], g + s->woff[l],
+                             s->fin[l], st));
+    SG_HIP(launch_row_sums((const __bf16*)s->dZT[cur].p, s->width, B, B, g + s->boff[l], st));
+    if (l > 0) {
+      GemmArgs d{};
+      d.A = (const __bf16*)s->dZ[cur].p;
+      d.lda = s->width;
+      d.B = (const __bf16*)s->WbT[l].p;
+      d.ldb = s->width;
+      d.M = B;
+      d.N = s->width;
+      d.K = s->width;
+      d.outb = (__bf16*)s->dZ[1 - cur].p;
+      d.ldob = s->width;
+      d.outbT = (__bf16*)s->dZT[1 - cur].p;
+      d.ldobT = B;
+      d.zprev = (const float*)s->Z[l - 1].p;
+      d.ldz = s->width;
+      SG_HIP(launch_gemm(EPI_BWD_DX, d, 1, st));
+      cur = 1 - cur;
+    }
+  }
+  return HJG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hjg_surrogate_create(hjg_ctx* ctx, int32_t n, int32_t width, int32_t depth, uint64_t seed, hjg_surrogate** out) {
+  if (!ctx || !out) return fail(HJG_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1 || n > 96) return fail(HJG_EINVAL, "n must be in [1, 96]");
+  if (width < 32 || width > 1024 || width % 32) return fail(HJG_EINVAL, "width must be a multiple of 32 in [32, 1024]");
+  if (depth < 1 || depth > 16) return fail(HJG_EINVAL, "depth must be in [1, 16]");
+  int device = 0;
+  SG_HIP(hipGetDevice(&device));
+  auto* s = new hjg_surrogate();
+  s->ctx = ctx;
+  s->device = device;
+  s->n = n;
+  s->width = width;
+  s->depth = depth;
+  s->nin = s->nout = n + 1;
+  s->in_p = round32(s->nin);
+  s->out_p = round32(s->nout);
+  s->L = depth + 1;
+  int64_t off = 0;
+  for (int l = 0; l < s->L; ++l) {
+    s->fin.push_back(l == 0 ? s->in_p : width);
+    s->fout.push_back(l == depth ? s->out_p : width);
+    s->tin.push_back(l == 0 ? s->nin : width);
+    s->tout.push_back(l == depth ? s->nout : width);
+    s->woff.push_back(off);
+    off += (int64_t)s->fin[l] * s->fout[l];
+    s->boff.push_back(off);
+    off += s->fout[l];
+  }
+  s->P = off;
+  int rc = 0;
+  auto cleanup = [&](int code) {
+    hjg_surrogate_destroy(s);
+    return code;
+  };
+  for (Buf* b : {&s->w, &s->g, &s->m, &s->v})
+    if ((rc = grow(*b, s->P * 4))) return cleanup(rc);
+  s->Wb.resize(s->L);
+  s->WbT.resize(s->L);
+  for (int l = 0; l < s->L; ++l) {
+    if ((rc = grow(s->Wb[l], (size_t)s->fin[l] * s->fout[l] * 2))) return cleanup(rc);
+    if ((rc = grow(s->WbT[l], (size_t)s->fin[l] * s->fout[l] * 2))) return cleanup(rc);
+  }
+  if ((rc = grow(s->norm, 4 * s->nin * 4))) return cleanup(rc);
+  if ((rc = grow(s->lw, s->out_p * 4))) return cleanup(rc);
+  // He-style uniform initial weights (zero padding, zero biases); identity normalisation
+  std::vector<float> hw(s->P, 0.f);
+  uint64_t st = seed ^ 0x5DEECE66Dull;
+  for (int l = 0; l < s->L; ++l) {
+    const double lim = 0.5 * std::sqrt(6.0 / s->tin[l]);
+    for (int o = 0; o < s->tout[l]; ++o)
+      for (int i = 0; i < s->tin[l]; ++i)
+        hw[s->woff[l] + (int64_t)o * s->fin[l] + i] = (float)((2.0 * uniform01(st) - 1.0) * lim);
+  }
+  std::vector<float> hn(4 * s->nin, 0.f);
+  for (int i = 0; i < s->nin; ++i) hn[s->nin + i] = hn[3 * s->nin + i] = 1.f;
+  if (hipMemcpy(s->w.p, hw.data(), s->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->norm.p, hn.data(), hn.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(s->m.p, 0, s->P * 4) != hipSuccess || hipMemset(s->v.p, 0, s->P * 4) != hipSuccess ||
+      hipMemset(s->g.p, 0, s->P * 4) != hipSuccess)
+    return cleanup(fail(HJG_EHIP, "surrogate initialisation copy failed"));
+  if ((rc = refresh_bf16(s, nullptr))) return cleanup(rc);
+  if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(HJG_EHIP, "surrogate initialisation failed"));
+  *out = s;
+  return HJG_OK;
+}
+
+void hjg_surrogate_destroy(hjg_surrogate* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  std::vector<Buf*> all = {&s->w, &s->g, &s->m, &s->v, &s->norm, &s->lw, &s->X0, &s->X0T, &s->Y, &s->T, &s->dY,
+                           &s->dYT, &s->part, &s->bl, &s->acc, &s->perm, &s->Xall, &s->Tall, &s->sv, &s->sg,
+                           &s->tq, &s->flags, &s->bcount, &s->total, &s->index, &s->xfb, &s->vfb, &s->gfb,
+                           &s->dZ[0], &s->dZ[1], &s->dZT[0], &s->dZT[1]};
+  for (auto& b : s->Wb) all.push_back(&b);
+  for (auto& b : s->WbT) all.push_back(&b);
+  for (auto& b : s->Z) all.push_back(&b);
+  for (auto& b : s->X) all.push_back(&b);
+  for (auto& b : s->XT) all.push_back(&b);
+  for (Buf* b : all)
+    if (b->p) (void)hipFree(b->p);
+  delete s;
+}
+
+int hjg_surrogate_param_count(const hjg_surrogate* s, int64_t* count) {
+  if (!s || !count) return fail(HJG_EINVAL, "NULL argument");
+  int64_t c = 0;
+  for (int l = 0; l < s->L; ++l) c += (int64_t)s->tin[l] * s->tout[l] + s->tout[l];
+  *count = c;
+  return HJG_OK;
+}
+
+int hjg_surrogate_set_params(hjg_surrogate* s, const float* params, const float* norm) {
+  if (!s || !params || !norm) return fail(HJG_EINVAL, "NULL argument");
+  for (int i = 0; i < s->nin; ++i)
+    if (!(norm[s->nin + i] > 0) || !(norm[3 * s->nin + i] > 0)) return fail(HJG_EINVAL, "std entries must be > 0");
+  std::vector<float> hw(s->P, 0.f);
+  int64_t k = 0;
+  for (int l = 0; l < s->L; ++l) {
+    for (int o = 0; o < s->tout[l]; ++o)
+      for (int i = 0; i < s->tin[l]; ++i) hw[s->woff[l] + (int64_t)o * s->fin[l] + i] = params[k++];
+    for (int o = 0; o < s->tout[l]; ++o) hw[s->boff[l] + o] = params[k++];
+  }
+  SG_HIP(hipMemcpy(s->w.p, hw.data(), s->P * 4, hipMemcpyHostToDevice));
+  SG_HIP(hipMemcpy(s->norm.p, norm, 4 * s->nin * 4, hipMemcpyHostToDevice));
+  SG_HIP(hipMemset(s->m.p, 0, s->P * 4));
+  SG_HIP(hipMemset(s->v.p, 0, s->P * 4));
+  s->step = 0;
+  int rc = refresh_bf16(s, nullptr);
+  if (rc) return rc;
+  SG_HIP(hipDeviceSynchronize());
+  return HJG_OK;
+}
+
+int hjg_surrogate_get_params(const hjg_surrogate* s, float* params, float* norm) {
+  if (!s || !params) return fail(HJG_EINVAL, "NULL argument");
+  SG_HIP(hipDeviceSynchronize());
+  std::vector<float> hw(s->P);
+  SG_HIP(hipMemcpy(hw.data(), s->w.p, s->P * 4, hipMemcpyDeviceToHost));
+  int64_t k = 0;
+  for (int l = 0; l < s->L; ++l) {
+    for (int o = 0; o < s->tout[l]; ++o)
+      for (int i = 0; i < s->tin[l]; ++i) params[k++] = hw[s->woff[l] + (int64_t)o * s->fin[l] + i];
+    for (int o = 0; o < s->tout[l]; ++o) params[k++] = hw[s->boff[l] + o];
+  }
+  if (norm) SG_HIP(hipMemcpy(norm, s->norm.p, 4 * s->nin * 4, hipMemcpyDeviceToHost));
+  return HJG_OK;
+}
+
+int hjg_surrogate_predict(hjg_surrogate* s, int64_t Q, const float* x, const float* t, float* v, float* grad,
+                          void* hip_stream) {
+  if (!s) return fail(HJG_EINVAL, "surrogate is NULL");
+  if (Q < 0) return fail(HJG_EINVAL, "Q must be >= 0");
+  if (Q == 0) return HJG_OK;
+  if (!x || !t || !v || !grad) return fail(HJG_EINVAL, "x, t, v and grad are required");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t chunk = 65536;
+  int rc;
+  if ((rc = ensure_batch(s, std::min(Q, chunk), false))) return rc;
+  for (int64_t r0 = 0; r0 < Q; r0 += chunk) {
+    const int64_t rows = std::min(chunk, Q - r0);
+    SG_HIP(launch_prep_inputs(x + r0, Q, t + r0, s->n, rows, s->in_p, nrm(s, 0), nrm(s, 1), (__bf16*)s->X0.p,
+                              nullptr, st));
+    if ((rc = forward(s, rows, false, st))) return rc;
+    SG_HIP(launch_post_outputs((const float*)s->Y.p, s->n, rows, s->out_p, nrm(s, 2), nrm(s, 3), v + r0, grad + r0,
+                               Q, st));
+  }
+  return HJG_OK;
+}
+
+namespace {
+
+int set_loss_weights(hjg_surrogate* s, double grad_weight, hipStream_t st) {
+  std::vector<float> w(s->out_p, 0.f);
+  w[0] = 1.f;
+  for (int j = 1; j < s->nout; ++j) w[j] = (float)(grad_weight / s->n);
+  SG_HIP(hipMemcpyAsync(s->lw.p, w.data(), w.size() * 4, hipMemcpyHostToDevice, st));
+  SG_HIP(hipStreamSynchronize(st));
+  return HJG_OK;
+}
+
+}  // namespace
+
+int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x, const float* t, const float* v,
+                            const float* grad, double grad_weight, double* loss, float* grads, void* hip_stream) {
+  if (!s || !loss) return fail(HJG_EINVAL, "NULL argument");
+  if (B < 32 || B % 32) return fail(HJG_EINVAL, "B must be a positive multiple of 32");
+  if (!x || !t || !v || !grad) return fail(HJG_EINVAL, "x, t, v and grad are required");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc;
+  if ((rc = ensure_batch(s, B, true))) return rc;
+  if ((rc = set_loss_weights(s, grad_weight, st))) return rc;
+  SG_HIP(launch_prep_inputs(x, B, t, s->n, B, s->in_p, nrm(s, 0), nrm(s, 1), (__bf16*)s->X0.p, (__bf16*)s->X0T.p,
+                            st));
+  SG_HIP(launch_prep_targets(v, grad, s->n, B, s->out_p, nrm(s, 2), nrm(s, 3), (float*)s->T.p, st));
+  SG_HIP(hipMemsetAsync(s->acc.p, 0, 8, st));
+  if ((rc = forward(s, B, true, st))) return rc;
+  if ((rc = backward(s, B, st))) return rc;
+  double l = 0.0;
+  SG_HIP(hipMemcpyAsync(&l, s->acc.p, 8, hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  *loss = l / (double)B;
+  if (grads) {
+    std::vector<float> hg(s->P);
+    SG_HIP(hipMemcpy(hg.data(), s->g.p, s->P * 4, hipMemcpyDeviceToHost));
+    int64_t k = 0;
+    for (int l2 = 0; l2 < s->L; ++l2) {
+      for (int o = 0; o < s->tout[l2]; ++o)
+        for (int i = 0; i < s->tin[l2]; ++i) grads[k++] = hg[s->woff[l2] + (int64_t)o * s->fin[l2] + i];
+      for (int o = 0; o < s->tout[l2]; ++o) grads[k++] = hg[s->boff[l2] + o];
+    }
+  }
+  return HJG_OK;
+}
+
+int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float* t, const float* v,
+                        const float* grad, const hjg_train_cfg* cfg, double* loss_hist, void* hip_stream) {
+  if (!s || !cfg) return fail(HJG_EINVAL, "NULL argument");
+  if (!x || !t || !v || !grad) return fail(HJG_EINVAL, "x, t, v and grad are required");
+  const int B = cfg->batch;
+  if (B < 32 || B % 32 || B > (1 << 20)) return fail(HJG_EINVAL, "batch must be a multiple of 32 in [32, 2^20]");
+  if (M < B) return fail(HJG_EINVAL, "need at least one full batch of training rows");
+  if (cfg->epochs < 1 || !(cfg->lr > 0) || !(cfg->lr_min >= 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) ||
+      !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0) || !(cfg->weight_decay >= 0))
+    return fail(HJG_EINVAL, "invalid training configuration");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc;
+  if ((rc = ensure_batch(s, B, true))) return rc;
+  if ((rc = set_loss_weights(s, cfg->grad_weight, st))) return rc;
+  // normalisation from the training data
+  float* nm = (float*)s->norm.p;
+  SG_HIP(launch_feature_stats(x, M, s->n, M, nm, nm + s->nin, st));
+  SG_HIP(launch_feature_stats(t, M, 1, M, nm + s->n, nm + s->nin + s->n, st));
+  SG_HIP(launch_feature_stats(v, M, 1, M, nm + 2 * s->nin, nm + 3 * s->nin, st));
+  SG_HIP(launch_feature_stats(grad, M, s->n, M, nm + 2 * s->nin + 1, nm + 3 * s->nin + 1, st));
+  // the whole normalised training set, inputs in bfloat16
+  if ((rc = grow(s->Xall, (size_t)M * s->in_p * 2))) return rc;
+  if ((rc = grow(s->Tall, (size_t)M * s->out_p * 4))) return rc;
+  if ((rc = grow(s->perm, (size_t)M * 4))) return rc;
+  SG_HIP(launch_prep_inputs(x, M, t, s->n, M, s->in_p, nrm(s, 0), nrm(s, 1), (__bf16*)s->Xall.p, nullptr, st));
+  SG_HIP(launch_prep_targets(v, grad, s->n, M, s->out_p, nrm(s, 2), nrm(s, 3), (float*)s->Tall.p, st));
+  const int64_t steps_per_epoch = M / B;
+  const int64_t total = steps_per_epoch * cfg->epochs;
+  std::vector<int> perm(M);
+  uint64_t seed = cfg->seed;
+  int64_t k = 0;
+  for (int e = 0; e < cfg->epochs; ++e) {
+    for (int64_t i = 0; i < M; ++i) perm[i] = (int)i;
+    for (int64_t i = M - 1; i > 0; --i) {        // Fisher-Yates
+      const int64_t j = (int64_t)(splitmix64(seed) % (uint64_t)(i + 1));
+      std::swap(perm[i], perm[j]);
+    }
+    SG_HIP(hipMemcpyAsync(s->perm.p, perm.data(), (size_t)M * 4, hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemsetAsync(s->acc.p, 0, 8, st));
+    for (int64_t b = 0; b < steps_per_epoch; ++b, ++k) {
+      SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p + b * B, B,
+                           s->in_p, s->out_p, (__bf16*)s->X0.p, (__bf16*)s->X0T.p, (float*)s->T.p, st));
+      if ((rc = forward(s, B, true, st))) return rc;
+      if ((rc = backward(s, B, st))) return rc;
+      ++s->step;
+      const double lr = cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * (double)k / total));
+      const float bc1 = (float)(1.0 - std::pow(cfg->beta1, (double)s->step));
+      const float bc2 = (float)(1.0 - std::pow(cfg->beta2, (double)s->step));
+      SG_HIP(launch_adamw((float*)s->w.p, (const float*)s->g.p, (float*)s->m.p, (float*)s->v.p, s->P, (float)lr,
+                          (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps, (float)cfg->weight_decay, bc1, bc2,
+                          st));
+      if ((rc = refresh_bf16(s, st))) return rc;
+    }
+    double acc = 0.0;
+    SG_HIP(hipMemcpyAsync(&acc, s->acc.p, 8, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));   // the host buffer `perm` is reused next epoch
+    if (loss_hist) loss_hist[e] = acc / ((double)steps_per_epoch * B);
+  }
+  return HJG_OK;
+}
+
+int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, int64_t Q, const float* x, double t,
+                        int32_t N_s, int32_t K_s, int32_t N_fb, int32_t K_fb, double tol, uint32_t time_step,
+                        float* v, float* grad, uint8_t* fell_back, int64_t* n_fallback, void* hip_stream) {
+  if (!ctx || !s || !p || !n_fallback) return fail(HJG_EINVAL, "NULL argument");
+  if (p->n != s->n) return fail(HJG_EINVAL, "problem dimension differs from the surrogate's");
+  if (Q < 0) return fail(HJG_EINVAL, "Q must be >= 0");
+  if (!(tol > 0)) return fail(HJG_EINVAL, "tol must be > 0 (it decides the fallback)");
+  *n_fallback = 0;
+  if (Q == 0) return HJG_OK;
+  if (!x || !v || !grad || !fell_back) return fail(HJG_EINVAL, "x, v, grad and fell_back are required");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc;
+  const int n = s->n;
+  if ((rc = grow(s->sv, Q * 4)) || (rc = grow(s->sg, (size_t)Q * n * 4)) || (rc = grow(s->tq, Q * 4)) ||
+      (rc = grow(s->index, Q * 4)) || (rc = grow(s->bcount, ((Q + 255) / 256 + 1) * 4)) || (rc = grow(s->total, 64)))
+    return rc;
+  // 1. the surrogate's value and gradient at (x, t)
+  SG_HIP(launch_fill((float*)s->tq.p, (float)t, Q, st));
+  if ((rc = hjg_surrogate_predict(s, Q, x, (const float*)s->tq.p, (float*)s->sv.p, (float*)s->sg.p, st))) return rc;
+  // 2. Picard from the warm start (v^(0), p^(0)) = surrogate; the per-state
+  //    relative change of the last iteration decides the fallback
+  rc = hjg_picard_sweep(ctx, p, Q, x, t, N_s, K_s, tol, time_step, (const float*)s->sg.p, (const float*)s->sv.p, v,
+                        grad, nullptr, nullptr, fell_back, nullptr, nullptr, hip_stream);
+  if (rc < 0) return rc;
+  // 3. plain Monte Carlo (no warm start) on the flagged states
+  int nb = 0;
+  SG_HIP(launch_compact_count(fell_back, Q, (int*)s->bcount.p, &nb, st));
+  SG_HIP(launch_compact_scan((int*)s->bcount.p, nb, (int*)s->total.p, st));
+  SG_HIP(launch_compact_write(fell_back, Q, (const int*)s->bcount.p, (int*)s->index.p, st));
+  int count = 0;
+  SG_HIP(hipMemcpyAsync(&count, s->total.p, 4, hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  *n_fallback = count;
+  if (count > 0) {
+    if ((rc = grow(s->xfb, (size_t)count * n * 4)) || (rc = grow(s->vfb, (size_t)count * 4)) ||
+        (rc = grow(s->gfb, (size_t)count * n * 4)))
+      return rc;
+    SG_HIP(launch_gather_soa(x, n, Q, (const int*)s->index.p, count, (float*)s->xfb.p, st));
+    rc = hjg_picard_sweep(ctx, p, count, (const float*)s->xfb.p, t, N_fb, K_fb, 0.0, time_step, nullptr, nullptr,
+                          (float*)s->vfb.p, (float*)s->gfb.p, nullptr, nullptr, nullptr, nullptr, nullptr, hip_stream);
+    if (rc < 0) return rc;
+    SG_HIP(launch_scatter_soa((const float*)s->vfb.p, 1, count, (const int*)s->index.p, Q, v, st));
+    SG_HIP(launch_scatter_soa((const float*)s->gfb.p, n, count, (const int*)s->index.p, Q, grad, st));
+  }
+  return HJG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+"""The surrogate network's GPU kernels against the FP64 reference, training,
+and the surrogate-accelerated sweep's fallback logic (runs on an MI355X)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp, philox
+from tests._helpers import gpu_problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2605_18566_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def layers_from_flat(flat, sizes):
+    out, k = [], 0
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        W = flat[k:k + fin * fout].reshape(fout, fin)
+        k += fin * fout
+        b = flat[k:k + fout]
+        k += fout
+        out.append((W.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+def flat_from_layers(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers])
+
+
+def bf16(a):
+    return philox.round_bf16(np.asarray(a, dtype=np.float64))
+
+
+def random_net(n, width, depth, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [n + 1] + [width] * depth + [n + 1]
+    layers = mlp.init_params(sizes, rng)
+    layers = [(W, rng.normal(0, 0.05, b.shape)) for W, b in layers]
+    norm = np.stack([rng.normal(0, 0.3, n + 1), rng.uniform(0.5, 2.0, n + 1),
+                     rng.normal(0, 0.3, n + 1), rng.uniform(0.5, 2.0, n + 1)])
+    return sizes, layers, norm
+
+
+@pytest.mark.parametrize("n,width,depth", [(8, 64, 2), (45, 256, 4)])
+def test_forward_matches_oracle(ctx, n, width, depth):
+    from paper_2605_18566_amd import Surrogate
+    sizes, layers, norm = random_net(n, width, depth, 1)
+    sur = Surrogate(ctx, n, width, depth)
+    sur.set_params(flat_from_layers(layers), norm)
+    rng = np.random.default_rng(2)
+    Q = 1000
+    x = rng.normal(0, 1.5, (n, Q)).astype(np.float32)
+    t = rng.uniform(0.1, 1.0, Q).astype(np.float32)
+    v, g = sur.predict(to_dev(x), to_dev(t))
+    torch.cuda.synchronize()
+    # reference: the same bfloat16-rounded weights and inputs, FP64 arithmetic
+    lw = [(bf16(W), b) for W, b in layers]
+    xt = np.concatenate([x.T, t[:, None]], 1).astype(np.float64)
+    X = bf16((xt - norm[0]) / norm[1])
+    Y, _ = mlp.forward(lw, X)
+    out = Y * norm[3] + norm[2]
+    dv = v.cpu().numpy() - out[:, 0]
+    dg = g.cpu().numpy().T - out[:, 1:]
+    assert np.linalg.norm(dv) <= 1e-2 * np.linalg.norm(out[:, 0])
+    assert np.linalg.norm(dg) <= 1e-2 * np.linalg.norm(out[:, 1:])
+    sur.close()
+
+
+@pytest.mark.parametrize("n,width,depth", [(8, 64, 2), (45, 256, 4)])
+def test_loss_and_gradients_match_oracle(ctx, n, width, depth):
+    from paper_2605_18566_amd import Surrogate
+    sizes, layers, norm = random_net(n, width, depth, 3)
+    sur = Surrogate(ctx, n, width, depth)
+    sur.set_params(flat_from_layers(layers), norm)
+    rng = np.random.default_rng(4)
+    B = 256
+    x = rng.normal(0, 1.5, (n, B)).astype(np.float32)
+    t = rng.uniform(0.1, 1.0, B).astype(np.float32)
+    v = rng.normal(0, 1, B).astype(np.float32)
+    gr = rng.normal(0, 1, (n, B)).astype(np.float32)
+    lam = 0.8
+    loss, grads = sur.loss_grad(to_dev(x), to_dev(t), to_dev(v), to_dev(gr), lam)
+    lw = [(bf16(W), b) for W, b in layers]
+    xt = np.concatenate([x.T, t[:, None]], 1).astype(np.float64)
+    X = bf16((xt - norm[0]) / norm[1])
+    T = (np.concatenate([v[:, None], gr.T], 1) - norm[2]) / norm[3]
+    ref_loss, ref_grads = mlp.loss_and_grads(lw, X, T, lam)
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss
+    got = layers_from_flat(grads, sizes)
+    for (gW, gb), (rW, rb) in zip(got, ref_grads):
+        assert np.linalg.norm(gW - rW) <= 3e-2 * np.linalg.norm(rW)
+        assert np.linalg.norm(gb - rb) <= 3e-2 * np.linalg.norm(rb) + 1e-7
+    sur.close()
+
+
+def test_params_round_trip_and_count(ctx):
+    from paper_2605_18566_amd import Surrogate
+    sur = Surrogate(ctx, 45, 256, 4, seed=9)
+    assert sur.param_count() == 221230
+    p, nm = sur.get_params()
+    sur.set_params(p, nm)
+    p2, nm2 = sur.get_params()
+    np.testing.assert_array_equal(p, p2)
+    np.testing.assert_array_equal(nm, nm2)
+    sur.close()
+
+
+def test_training_reduces_loss_on_a_smooth_target(ctx):
+    from paper_2605_18566_amd import Surrogate, TrainConfig
+    n, M = 6, 16384
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-2, 2, (n, M)).astype(np.float32)
+    t = rng.uniform(0.2, 1.0, M).astype(np.float32)
+    # value sqrt(|x_pos|^2 + t) - 1 with its exact gradient
+    r = np.sqrt(x[0] ** 2 + x[1] ** 2 + t)
+    v = (r - 1.0).astype(np.float32)
+    g = np.zeros((n, M), np.float32)
+    g[0], g[1] = x[0] / r, x[1] / r
+    sur = Surrogate(ctx, n, 128, 3, seed=1)
+    hist = sur.train(to_dev(x), to_dev(t), to_dev(v), to_dev(g),
+                     TrainConfig(epochs=30, batch=1024, lr=3e-3, lr_min=1e-4, seed=3))
+    print("training loss per epoch:", np.round(hist, 5).tolist())
+    assert hist[-1] < 0.1 * hist[0]
+    # held-out states
+    xh = rng.uniform(-2, 2, (n, 2000)).astype(np.float32)
+    th = rng.uniform(0.2, 1.0, 2000).astype(np.float32)
+    vp, gp = sur.predict(to_dev(xh), to_dev(th))
+    rh = np.sqrt(xh[0] ** 2 + xh[1] ** 2 + th)
+    err = np.sqrt(np.mean((vp.cpu().numpy() - (rh - 1)) ** 2))
+    assert err < 0.05, err
+    sur.close()
+
+
+def _small_problem():
+    w = workloads.C5.resized(n=9, box=workloads.dubins_box(3))
+    return w, dict(w.problem_fields())
+
+
+def test_surrogate_sweep_fallback_everywhere_equals_plain_sweep(ctx):
+    from paper_2605_18566_amd import Surrogate, picard_sweep, surrogate_sweep
+    w, fields = _small_problem()
+    x = to_dev(np.ascontiguousarray(workloads.queries(w, Q=700, trial=2).T))
+    spec = gpu_problem(fields)
+    sur = Surrogate(ctx, 9, 64, 2, seed=4)       # untrained: disagrees with Monte Carlo everywhere
+    v, g, fb, nfb = surrogate_sweep(ctx, sur, spec, x, 1.0, N_s=1024, K_s=1, N_fb=2048, K_fb=3, tol=1e-9)
+    assert nfb == 700 and int(fb.sum().item()) == 700
+    ref = picard_sweep(ctx, spec, x, 1.0, 2048, 3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(v.cpu().numpy(), ref.v.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(g.cpu().numpy(), ref.grad.cpu().numpy(), rtol=1e-4, atol=1e-5)
+    sur.close()
+
+
+def test_surrogate_sweep_without_fallback_is_the_warm_started_sweep(ctx):
+    from paper_2605_18566_amd import Surrogate, picard_sweep, surrogate_sweep
+    w, fields = _small_problem()
+    x = to_dev(np.ascontiguousarray(workloads.queries(w, Q=500, trial=3).T))
+    spec = gpu_problem(fields)
+    sur = Surrogate(ctx, 9, 64, 2, seed=5)
+    v, g, fb, nfb = surrogate_sweep(ctx, sur, spec, x, 1.0, N_s=1024, K_s=2, N_fb=2048, K_fb=3, tol=1e30)
+    assert nfb == 0 and int(fb.sum().item()) == 0
+    sv, sg = sur.predict(x, 1.0)
+    # same tolerance: the loop stops after the first iteration in both calls
+    ref = picard_sweep(ctx, spec, x, 1.0, 1024, 2, tol=1e30, p0=sg.contiguous(), v0=sv.contiguous())
+    torch.cuda.synchronize()
+    assert ref.iters_done == 1
+    np.testing.assert_array_equal(v.cpu().numpy(), ref.v.cpu().numpy())
+    sur.close()
+
+
+def test_partial_fallback_scatters_to_the_right_states(ctx):
+    from paper_2605_18566_amd import Surrogate, picard_sweep, surrogate_sweep
+    w, fields = _small_problem()
+    Q = 900
+    x = to_dev(np.ascontiguousarray(workloads.queries(w, Q=Q, trial=4).T))
+    spec = gpu_problem(fields)
+    sur = Surrogate(ctx, 9, 64, 2, seed=6)
+    tol = 0.05
+    v, g, fb, nfb = surrogate_sweep(ctx, sur, spec, x, 1.0, N_s=1024, K_s=2, N_fb=2048, K_fb=3, tol=tol)
+    fb = fb.cpu().numpy().astype(bool)
+    assert 0 < nfb < Q and fb.sum() == nfb
+    sv, sg = sur.predict(x, 1.0)
+    warm = picard_sweep(ctx, spec, x, 1.0, 1024, 2, tol=tol, p0=sg.contiguous(), v0=sv.contiguous())
+    plain = picard_sweep(ctx, spec, x, 1.0, 2048, 3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(warm.flags.cpu().numpy().astype(bool), fb)
+    v = v.cpu().numpy()
+    np.testing.assert_array_equal(v[~fb], warm.v.cpu().numpy()[~fb])
+    np.testing.assert_allclose(v[fb], plain.v.cpu().numpy()[fb], rtol=1e-5, atol=1e-6)
+    sur.close()

@@ -65,7 +65,7 @@ def test_version_and_error_paths_without_device(lib):
     rc = lib.hjg_value_grad(None, C.byref(p), 4, None, 0.5, 16, 0, 0, None, None, None, None, None, 0, None)
     assert rc == _lib.HJG_EINVAL and b"context" in lib.hjg_last_error()
     rc = lib.hjg_picard_sweep(None, C.byref(p), 4, None, 0.5, 16, 1, 0.0, 0, None, None, None, None, None, None,
-                              None, None, None)
+                              None, None, None, None)
     assert rc == _lib.HJG_EINVAL
     lib.hjg_ctx_destroy(None)
 
