@@ -2,14 +2,16 @@
 
 One step = one full Picard sweep (Algorithm 1: K frozen-coefficient
 iterations, each drawing N samples per query and returning v and Dv) over the
-n = 45 workload: 15 stacked relative Dubins pairs, 262,144 queries,
-N = 65,536 bfloat16 common draws, K = 5, nu = 0.01, t = 1, Laplace shift from
-the previous iterate.  The metric is query.samples per second:
+n = 45 workload: 15 stacked relative Dubins pairs (tube coefficient
+min{0, H}), 262,144 queries, N = 65,536 bfloat16 common draws, K = 5,
+nu = 0.01, t = 1, Laplace shift from the previous iterate.  The metric is query.samples per second:
 Q * N * K / (seconds per step).
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (the pair loop, timed by HIP events around every launch inside the timed
-region) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+region), the FP64 CPU oracle timed on a bounded sample of the same workload,
+the estimator's health on that workload (ESS, Picard residuals) and the
+surrogate-vs-plain study at equal RMS value error.
 """
 from __future__ import annotations
 
@@ -66,6 +68,99 @@ def measured_traffic():
     return int(mt.group(1)) if h.hexdigest()[:16] == mh.group(1) else None
 
 
+def surrogate_study(ctx, stream):
+    """Surrogate-accelerated vs plain sweep at equal RMS value error (n = 45).
+
+    Workload: the n = 45 disc-union datum with H = |p|^2/2 (exact Cole-Hopf
+    case), nu = 0.01, t = 1, bf16 common draws, tilt.  The network
+    (46 -> 4 x 256 SiLU -> 46) is trained on 2M (x, t) labels of the plain sweep
+    (10 horizons t = 0.1 .. 1, 200,000 states each, N = 65,536, K = 5).  The
+    judge is the plain sweep at N = 2^20, K = 5 with another seed, on 262,144
+    fresh states at t = 1.  RMS of v against the judge; wall time per sweep
+    (median of 3, synchronised).
+    """
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, Surrogate, TrainConfig, picard_sweep, surrogate_sweep
+
+    w = workloads.C5Q
+    f = w.problem_fields()
+    dev = torch.device("cuda:0")
+
+    def timed(fn, reps=3):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return r, float(np.median(ts))
+
+    t0 = time.perf_counter()
+    xs, ts, vs, gs = [], [], [], []
+    horizons, per_h = 10, 200000
+    for j in range(horizons):
+        tj = (j + 1) / horizons
+        x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w, Q=per_h, trial=100 + j).T)).to(dev)
+        o = picard_sweep(ctx, ProblemSpec(**dict(f, seed=f["seed"] + 1000 + j)), x, tj, w.N, w.K, time_step=j,
+                         stream=stream)
+        xs.append(x)
+        ts.append(torch.full((per_h,), tj, device=dev))
+        vs.append(o.v.clone())
+        gs.append(o.grad.clone())
+    X, T = torch.cat(xs, 1).contiguous(), torch.cat(ts).contiguous()
+    V, G = torch.cat(vs).contiguous(), torch.cat(gs, 1).contiguous()
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    sur = Surrogate(ctx, w.n, 256, 4, seed=7)
+    t0 = time.perf_counter()
+    cfg = TrainConfig(epochs=40, batch=4096, lr=2e-3, lr_min=1e-5, weight_decay=1e-4, grad_weight=0.5, seed=11)
+    hist = sur.train(X, T, V, G, cfg, stream=stream)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, T, V, G, xs, ts, vs, gs
+    print(f"surrogate trained: labels {t_labels:.1f} s, training {t_train:.1f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}",
+          file=sys.stderr, flush=True)
+
+    x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to(dev)
+    spec = ProblemSpec(**f)
+    judge = picard_sweep(ctx, ProblemSpec(**dict(f, seed=f["seed"] + 777)), x, w.t, 1 << 20, w.K, time_step=3,
+                         stream=stream)
+    vj = judge.v.clone()
+    rms = lambda v: float(torch.sqrt(torch.mean((v - vj) ** 2)))
+    sv, _ = sur.predict(x, w.t)
+    plain, surr = [], []
+    for N in (1 << 12, 1 << 14, 1 << 16):
+        o, sec = timed(lambda: picard_sweep(ctx, spec, x, w.t, N, w.K, stream=stream))
+        plain.append({"N": N, "K": w.K, "rms_v": rms(o.v), "ms": sec * 1e3})
+    for tol in (1e-3, 1e-2):
+        for N in (1 << 12, 1 << 14, 1 << 16):
+            (v, g, fb, nfb), sec = timed(lambda: surrogate_sweep(ctx, sur, spec, x, w.t, N, 2, w.N, w.K, tol,
+                                                                 stream=stream))
+            surr.append({"N_s": N, "K_s": 2, "tol": tol, "rms_v": rms(v), "ms": sec * 1e3,
+                         "fallback": nfb / w.Q})
+    target = plain[-1]["rms_v"]
+    speedup = {}
+    for tol in (1e-3, 1e-2):
+        ok = [r["ms"] for r in surr if r["tol"] == tol and r["rms_v"] <= target]
+        speedup[f"tol={tol:g}"] = (plain[-1]["ms"] / min(ok)) if ok else None
+    sur.close()
+    return {"workload": f"{w.name}: n=45, H=|p|^2/2, 15-disc union, nu={w.nu}, t={w.t}, bf16 draws, Q={w.Q}",
+            "network": "46 -> 4 x 256 SiLU -> 46, bf16 MFMA forward/backward, fp32 master, AdamW",
+            "training": {"labels": horizons * per_h, "label_N": w.N, "label_K": w.K, "epochs": cfg.epochs,
+                         "label_seconds": t_labels, "train_seconds": t_train, "loss_first": float(hist[0]),
+                         "loss_last": float(hist[-1])},
+            "judge": {"N": 1 << 20, "K": w.K, "seed_offset": 777},
+            "surrogate_alone_rms_v": rms(sv),
+            "plain": plain, "surrogate": surr,
+            "target_rms_v": target,
+            "speedup_at_equal_rms": speedup}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -99,6 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=None, help="override Q (default: the workload's 262,144)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the equal-accuracy surrogate study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -162,6 +258,15 @@ def main():
     v = out.v.cpu().numpy()
     if not np.all(np.isfinite(v)):
         raise RuntimeError("non-finite values in the benchmark output")
+    ctx.set_timing(False)
+    health = {"resid_hist_last_step": None, "ess_median": float(np.median(out.ess.cpu().numpy())),
+              "ess_q10": float(np.quantile(out.ess.cpu().numpy(), 0.1)),
+              "coefficient_median_abs": float(np.median(np.abs(out.c.cpu().numpy())))}
+    chk = picard_sweep(ctx, spec, x, w.t, w.N, w.K, stream=stream)
+    health["resid_hist_last_step"] = [float(r) for r in chk.resid_hist]
+    study = None
+    if not args.no_surrogate:
+        study = surrogate_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -186,12 +291,15 @@ def main():
         "config": {"workload": f"{w.name}: plain Monte-Carlo Picard sweep", "n": w.n, "queries": w.Q,
                    "samples": w.N, "picard_iterations": w.K, "nu": w.nu, "t": w.t,
                    "draws": "bf16 common table (Philox4x32-10)", "tilt": "Laplace shift from previous iterate",
-                   "hamiltonian": w.ham, "datum": w.datum},
+                   "hamiltonian": w.ham, "coefficient": "min{0,H} (tube equation)" if w.tube else "H",
+                   "datum": w.datum},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                      "kernel": "pair loop (sweep_mfma_kernel<min_pair_disks, 48, 15>)", "kernel_ms_per_launch": per_launch_ms,
                      "launches_timed": launches, "alu_slots_per_pair": slots},
         "cpu_baseline": cpu,
+        "estimator_health": health,
+        "surrogate": study,
     }
     print(json.dumps(line))
 

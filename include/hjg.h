@@ -21,7 +21,7 @@
  * with |c| clipped to [c_min, c_max] and its sign kept, sign(0) = +1
  * (coefficient definition of Section 2.1, the regularised-coefficient lemma
  * and the remark on the coefficient's sign); for H = |p|^2/2 it is exactly
- * 1/delta.  The Laplace shift is theta = -sigma^2 c p (Section 2.4).
+ * 1/delta.  With the tube option H is replaced by min{0, H}.  The Laplace shift is theta = -sigma^2 c p (Section 2.4).
  *
  * Conventions shared by every entry point
  *  - Arrays marked "device" are device pointers on the context's GPU, owned by
@@ -114,6 +114,9 @@ typedef struct hjg_problem {
   int32_t grad_cv;         /* 1: subtract zbar in the gradient (control variate)    */
   uint64_t seed;           /* Philox key                                            */
   uint32_t problem_id;     /* < 65536; part of the Philox tag                       */
+  int32_t tube;            /* 1: the coefficient uses min{0, H} (the tube equation
+                              HJI-RCBRT-Visc, v_t + min{0,H} = (delta/2) Lap v);
+                              0: H as in Algorithm 1                                */
 } hjg_problem;
 
 typedef struct hjg_ctx hjg_ctx;

@@ -46,6 +46,7 @@ class Problem:
     grad_cv: bool = False
     seed: int = 0
     problem_id: int = 0
+    tube: bool = False        # coefficient from min{0, H} (tube equation HJI-RCBRT-Visc)
 
     @property
     def delta(self) -> float:
@@ -160,11 +161,15 @@ def coefficient(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
     (lemma on the regularised coefficient) and the clipping of |c| to
     [c_min, c_max] with the sign kept (remark on the sign of the coefficient);
     sign(0) is taken as +1.  For H = |p|^2/2 the exact constant 1/delta is used
-    with no regularisation (exact Cole-Hopf case).
+    with no regularisation (exact Cole-Hopf case).  For the tube equation
+    (HJI-RCBRT-Visc, v_t + min{0, H} = (delta/2) Lap v) H is replaced by
+    min{0, H}.
     """
     if pb.ham == "quadratic":
         return np.full(x.shape[0], 1.0 / pb.delta)
     H = hamiltonian(pb, x, p)
+    if pb.tube:
+        H = np.minimum(H, 0.0)
     c_raw = (2.0 / pb.delta) * H / (np.sum(p * p, axis=1) + pb.eta)
     sgn = np.where(c_raw < 0, -1.0, 1.0)
     return sgn * np.clip(np.abs(c_raw), pb.c_min, pb.c_max)

@@ -37,6 +37,7 @@ class Problem(C.Structure):
         ("grad_cv", C.c_int32),
         ("seed", C.c_uint64),
         ("problem_id", C.c_uint32),
+        ("tube", C.c_int32),
     ]
 
 

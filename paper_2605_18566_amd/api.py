@@ -36,6 +36,7 @@ class ProblemSpec:
     grad_cv: bool = False
     seed: int = 0
     problem_id: int = 0
+    tube: bool = False
 
     def to_c(self) -> _lib.Problem:
         p = _lib.Problem()
@@ -59,6 +60,7 @@ class ProblemSpec:
         p.grad_cv = int(bool(self.grad_cv))
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.problem_id = int(self.problem_id)
+        p.tube = int(bool(self.tube))
         return p
 
 

@@ -187,6 +187,7 @@ HamP ham_params(const hjg_problem* p) {
   h.eta = (float)p->eta;
   h.c_min = (float)p->c_min;
   h.c_max = (float)p->c_max;
+  h.tube = p->tube ? 1 : 0;
   return h;
 }
 
@@ -474,6 +475,7 @@ void copy_problem(hjg_problem* dst, const hjg_problem* src) {
   dst->grad_cv = src->grad_cv;
   dst->seed = src->seed;
   dst->problem_id = src->problem_id;
+  dst->tube = src->tube;
 }
 
 int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {

@@ -83,6 +83,7 @@ struct HamP {
   float inv_delta;      // 1 / delta
   float two_over_delta; // 2 / delta
   float eta, c_min, c_max;
+  int tube;             // use min{0, H}
 };
 
 // l(x) and D l(x) at one state held in registers (x[d] for d < n).  Same rules
@@ -187,13 +188,16 @@ __device__ inline float hamiltonian(const HamP& hp, const float* x, const float*
 
 // Frozen coefficient: c = (2/delta) H / (|p|^2 + eta), |c| clipped to
 // [c_min, c_max], sign kept, sign(0) = +1; exactly 1/delta for H = |p|^2/2.
+// The tube equation uses min{0, H} in place of H.
 template <int NM>
 __device__ inline float coefficient(const HamP& hp, const float* x, const float* p) {
   if (hp.kind == HJG_H_QUADRATIC) return hp.inv_delta;
   float pp = 0.f;
 #pragma unroll
   for (int d = 0; d < NM; ++d) if (d < hp.n) pp += p[d] * p[d];
-  const float raw = hp.two_over_delta * hamiltonian<NM>(hp, x, p) / (pp + hp.eta);
+  float H = hamiltonian<NM>(hp, x, p);
+  if (hp.tube) H = fminf(H, 0.f);
+  const float raw = hp.two_over_delta * H / (pp + hp.eta);
   const float mag = fminf(fmaxf(fabsf(raw), hp.c_min), hp.c_max);
   return raw < 0.f ? -mag : mag;
 }

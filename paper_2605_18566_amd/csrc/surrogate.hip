@@ -304,11 +304,13 @@ int hjg_surrogate_create(hjg_ctx* ctx, int32_t n, int32_t width, int32_t depth, 
   }
   if ((rc = grow(s->norm, 4 * s->nin * 4))) return cleanup(rc);
   if ((rc = grow(s->lw, s->out_p * 4))) return cleanup(rc);
-  // He-style uniform initial weights (zero padding, zero biases); identity normalisation
+  // Uniform initial weights, He scale sqrt(6/fan_in) for the SiLU layers and
+  // Glorot scale sqrt(6/(fan_in+fan_out)) for the linear output layer (zero
+  // padding, zero biases); identity normalisation
   std::vector<float> hw(s->P, 0.f);
   uint64_t st = seed ^ 0x5DEECE66Dull;
   for (int l = 0; l < s->L; ++l) {
-    const double lim = 0.5 * std::sqrt(6.0 / s->tin[l]);
+    const double lim = l < depth ? std::sqrt(6.0 / s->tin[l]) : std::sqrt(6.0 / (s->tin[l] + s->tout[l]));
     for (int o = 0; o < s->tout[l]; ++o)
       for (int i = 0; i < s->tin[l]; ++i)
         hw[s->woff[l] + (int64_t)o * s->fin[l] + i] = (float)((2.0 * uniform01(st) - 1.0) * lim);

@@ -74,6 +74,7 @@ CASES = {
                                   300, 1027),
     "dubins_n3_tilt": (dict(workloads.C2.problem_fields()), 1500, 4096 + 77),
     "dubins_n3_printed_sign": (dict(workloads.C2.problem_fields(), ham_p=(-1.0, 1.0, 1.0, 1.0)), 600, 2000),
+    "dubins_n3_plain_h": (dict(workloads.C2.problem_fields(), tube=False), 700, 3000),
     "dubins_n45_bf16": (dict(workloads.C5.problem_fields()), 600, 3000),
     "dubins_n12_fp32": (dict(workloads.C5.problem_fields(), n=12, sample_bf16=False), 700, 2500),
     "dubins_n30_bf16_cv": (dict(workloads.C5.problem_fields(), n=30, grad_cv=True), 400, 1500),
@@ -219,6 +220,7 @@ def test_picard_dubins_multi_iteration(ctx):
     # iterate feed the next coefficient, so compare with a per-query tolerance
     # scaled by the iteration count and require almost every query inside it.
     fields = dict(workloads.C2.problem_fields())
+    assert fields["tube"]
     Q, N, K, t = 1200, 4096, 3, 1.0
     out, ref, pb = _picard_both(ctx, fields, Q, N, K, t)
     sigma = np.sqrt(pb.delta * t)
@@ -230,6 +232,17 @@ def test_picard_dubins_multi_iteration(ctx):
     np.testing.assert_allclose(out.resid_hist, ref.resid_hist, rtol=2e-2, atol=1e-6)
     c = out.c.cpu().numpy()
     assert np.mean(np.abs(c - ref.c) <= 1e-3 * np.abs(ref.c) + 1e-3) >= 0.99
+    assert np.all(ref.c <= pb.c_min)             # min{0, H}: never a positive coefficient above c_min
+
+
+def test_picard_dubins_plain_h(ctx):
+    fields = dict(workloads.C2.problem_fields(), tube=False)
+    Q, N, K, t = 1000, 4096, 3, 1.0
+    out, ref, pb = _picard_both(ctx, fields, Q, N, K, t, trial=6)
+    sigma = np.sqrt(pb.delta * t)
+    v = out.v.cpu().numpy()
+    vt = 10 * value_tol(ref.v, ref.c, ref.theta, sigma, ref.lmax)
+    assert np.mean(np.abs(v - ref.v) <= vt) >= 0.995
 
 
 def test_picard_early_exit(ctx):

@@ -320,6 +320,18 @@ def test_coefficient_sign_clip_and_regularisation():
         assert np.sign(ci) == np.sign(ri) and 0.5 <= abs(ci) <= 20.0
 
 
+def test_tube_coefficient_uses_min_zero_h():
+    pb = model.Problem(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01, tube=True)
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-3, 3, (200, 3))
+    p = rng.normal(size=(200, 3))
+    H = model.hamiltonian(pb, x, p)
+    c = model.coefficient(pb, x, p)
+    assert np.all(c[H > 0] == pb.c_min)                  # min{0, H} = 0 -> +c_min
+    pb2 = model.Problem(**{**pb.__dict__, "tube": False})
+    np.testing.assert_array_equal(c[H < 0], model.coefficient(pb2, x, p)[H < 0])
+
+
 # ---------------------------------------------------------------- Picard loop
 def test_picard_quadratic_is_fixed_after_one_step_crn():
     pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=0.05, seed=3)

@@ -51,6 +51,7 @@ class Workload:
     cfg: int = 0
     time_steps: int = 1
     T: float = 1.0
+    tube: bool = False
 
     @property
     def seed(self) -> int:
@@ -63,7 +64,7 @@ class Workload:
         return dict(n=self.n, ham=self.ham, datum=self.datum, nu=self.nu, ham_p=tuple(self.ham_p),
                     datum_p=tuple(self.datum_p), eta=self.eta, c_min=self.c_min, c_max=self.c_max,
                     tilt=self.tilt, sample_mode=self.sample_mode, sample_bf16=self.sample_bf16,
-                    grad_cv=self.grad_cv, seed=self.seed)
+                    grad_cv=self.grad_cv, seed=self.seed, tube=self.tube)
 
 
 def queries(w: Workload, Q: Optional[int] = None, trial: int = 0) -> np.ndarray:
@@ -87,15 +88,22 @@ C1_QUAD = replace(C1, name="c1_quadratic_halfsq_n2", datum="half_sqnorm", datum_
 
 # Dubins pursuit-evasion in relative coordinates, disk of radius 0.5, nu = 0.01,
 # T = 1 in 10 horizons, 5 iterations, 65,536 queries, N = 65,536 common draws.
+# The Dubins game is a reachability (tube) problem: its coefficient uses
+# min{0, H} (tube equation of the paper's Dubins example).
 C2 = Workload("c2_dubins_n3", n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01, t=1.0,
               Q=65536, N=65536, K=5, box=dubins_box(1), tilt=True, sample_mode="crn_step", cfg=2,
-              time_steps=10, T=1.0)
+              time_steps=10, T=1.0, tube=True)
 
 # n = 45: 15 stacked relative Dubins pairs, nu = 0.01, T = 1, bfloat16 common
 # draws, N = 65,536, K = 5, 262,144 queries (the surrogate's inference size).
 C5 = Workload("c5_dubins15_n45", n=45, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
               t=1.0, Q=262144, N=65536, K=5, box=dubins_box(15), tilt=True, sample_mode="crn_step",
-              sample_bf16=True, cfg=5)
+              sample_bf16=True, cfg=5, tube=True)
+
+# The same n = 45 datum, draws and sizes with H = |p|^2/2, the exact Cole-Hopf
+# case (no quasi-linearisation defect): the workload of the equal-accuracy
+# surrogate study.
+C5Q = replace(C5, name="c5q_quadratic15_n45", ham="quadratic", tube=False, cfg=6)
 
 
 def horizons(w: Workload):
