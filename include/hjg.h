@@ -206,6 +206,32 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
                      double* resid_hist, int32_t* iters_done, void* hip_stream);
 
 /*
+ * Algorithm 1 for P independent problems of uneven dimension, sample count,
+ * state count, viscosity and iteration count in one call.  Problem p has
+ * Q_p = q_off[p+1] - q_off[p] states (q_off host [P+1], q_off[0] = 0), N[p]
+ * draws from its own common table (CRN_STEP only; time step 0; distinct
+ * problem_id or seed give distinct tables), K[p] iterations and horizon t[p]
+ * (host arrays [P]).  States: x_all device float32, problem p's [n_p][Q_p]
+ * block starts at element sum_{p'<p} n_p' Q_p'; grad_all has the same layout;
+ * v_all device [sum Q_p] at q_off[p].  All problems stop on the same
+ * relative-change tolerance tol (<= 0: run all K[p]).
+ *
+ * Problems that share a kernel specialisation share its launches: each
+ * Picard level is one pair-loop launch per specialisation over a work list
+ * of (problem, query block, sample split) items ordered heaviest first, one
+ * finalize launch per register bucket and one residual launch, and the whole
+ * loop over levels is recorded once into a HIP graph (problems with K[p] <= k
+ * drop out of level k; each has its own device stop flag).  resid_hist (host
+ * [P][max K], entries past K[p] zero) and iters (host [P]) are optional;
+ * giving either synchronises the stream.
+ */
+int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problems,
+                             const int64_t* q_off, const int32_t* N, const int32_t* K,
+                             const double* t, double tol, const float* x_all,
+                             float* v_all, float* grad_all, double* resid_hist,
+                             int32_t* iters, void* hip_stream);
+
+/*
  * ------------------------------------------------------------------------
  * Learned surrogate (x, t) -> (v, Dv).
  *

@@ -77,6 +77,10 @@ SIGNATURES = [
     ("hjg_value_grad", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,
                                  C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hjg_picard_sweep_batched", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                           C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int32), C.c_void_p]),
     ("hjg_surrogate_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                        C.POINTER(C.c_void_p)]),
     ("hjg_surrogate_destroy", None, [C.c_void_p]),

@@ -205,6 +205,58 @@ def picard_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: 
     return out
 
 
+# ------------------------------------------------------------------- batched
+@dataclass
+class BatchOut:
+    v: torch.Tensor           # [sum Q]
+    grad: torch.Tensor        # concatenated [n_p][Q_p] blocks
+    resid_hist: np.ndarray    # [P][max K]
+    iters: np.ndarray         # [P]
+    q_off: np.ndarray         # [P+1]
+    x_off: np.ndarray         # [P+1] element offsets of the [n_p][Q_p] blocks
+
+
+def picard_sweep_batched(ctx: Context, specs, xs, N, K, t, tol: float = 0.0, host_outputs: bool = True,
+                         x_all: Optional[torch.Tensor] = None, out: Optional[BatchOut] = None, stream=None):
+    """Algorithm 1 for several problems in one call (hjg_picard_sweep_batched).
+
+    specs: list of ProblemSpec; xs: list of [n_p][Q_p] CUDA tensors (or x_all
+    with the concatenated blocks); N, K, t: per-problem sequences.
+    """
+    P = len(specs)
+    if x_all is None:
+        for i, x in enumerate(xs):
+            _require_cuda(x, f"xs[{i}]")
+            if x.shape[0] != specs[i].n:
+                raise ValueError(f"xs[{i}] must have shape [n, Q]")
+        x_all = torch.cat([x.reshape(-1) for x in xs]).contiguous()
+        Qs = [x.shape[1] for x in xs]
+    else:
+        _require_cuda(x_all, "x_all")
+        Qs = [x.shape[1] if hasattr(x, "shape") else int(x) for x in xs]
+    q_off = np.zeros(P + 1, dtype=np.int64)
+    q_off[1:] = np.cumsum(Qs)
+    x_off = np.zeros(P + 1, dtype=np.int64)
+    x_off[1:] = np.cumsum([s.n * q for s, q in zip(specs, Qs)])
+    if out is None:
+        out = BatchOut(torch.empty(int(q_off[-1]), dtype=torch.float32, device=x_all.device),
+                       torch.empty(int(x_off[-1]), dtype=torch.float32, device=x_all.device),
+                       np.zeros((P, max(K))), np.zeros(P, dtype=np.int32), q_off, x_off)
+    probs = (_lib.Problem * P)(*[s.to_c() for s in specs])
+    qo = (C.c_int64 * (P + 1))(*q_off.tolist())
+    Na = (C.c_int32 * P)(*[int(v) for v in N])
+    Ka = (C.c_int32 * P)(*[int(v) for v in K])
+    ta = (C.c_double * P)(*[float(v) for v in t])
+    hist = (C.c_double * (P * max(K)))() if host_outputs else None
+    it = (C.c_int32 * P)() if host_outputs else None
+    check(_lib.lib().hjg_picard_sweep_batched(ctx.handle, P, probs, qo, Na, Ka, ta, float(tol), _ptr(x_all),
+                                              _ptr(out.v), _ptr(out.grad), hist, it, _stream(stream)))
+    if host_outputs:
+        out.resid_hist = np.array(list(hist)).reshape(P, max(K))
+        out.iters = np.array(list(it), dtype=np.int32)
+    return out
+
+
 # ----------------------------------------------------------------- surrogate
 @dataclass
 class TrainConfig:

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <tuple>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -61,6 +63,15 @@ struct hjg_ctx {
   int timing = 0;
   std::vector<hipEvent_t> ev;   // [2 * kMaxTimed]: begin/end per sweep launch
   int last_pairs = 0;           // event pairs used by the last call
+  // the last batched plan (workspace, argument records, work items, graph)
+  struct BatchPlan {
+    std::vector<char> key;
+    DevBuf ws, args, items;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> resid_off, ctrl_off;   // per problem, bytes into ws
+    std::vector<int> K;
+  } batch;
 };
 
 namespace {
@@ -69,12 +80,21 @@ constexpr int kMaxTimed = 256;
 
 namespace {
 
+void drop_batch_graph(hjg_ctx* ctx) {
+  if (ctx->batch.exec) (void)hipGraphExecDestroy(ctx->batch.exec);
+  if (ctx->batch.graph) (void)hipGraphDestroy(ctx->batch.graph);
+  ctx->batch.exec = nullptr;
+  ctx->batch.graph = nullptr;
+  ctx->batch.key.clear();
+}
+
 void drop_graphs(hjg_ctx* ctx) {
   for (auto& g : ctx->graphs) {
     (void)hipGraphExecDestroy(g.exec);
     (void)hipGraphDestroy(g.graph);
   }
   ctx->graphs.clear();
+  drop_batch_graph(ctx);
 }
 
 // Grow a workspace buffer; any growth invalidates recorded graphs (they hold
@@ -321,7 +341,8 @@ void hjg_ctx_destroy(hjg_ctx* ctx) {
   (void)hipDeviceSynchronize();
   drop_graphs(ctx);
   for (DevBuf* b : {&ctx->pm, &ctx->pS, &ctx->pS2, &ctx->pG, &ctx->pZ, &ctx->vprev, &ctx->cwork, &ctx->thwork,
-                    &ctx->blockpart, &ctx->resid, &ctx->ctrl, &ctx->table, &ctx->zbar})
+                    &ctx->blockpart, &ctx->resid, &ctx->ctrl, &ctx->table, &ctx->zbar, &ctx->batch.ws,
+                    &ctx->batch.args, &ctx->batch.items})
     if (b->p) (void)hipFree(b->p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -715,3 +736,360 @@ int hjg_sweep_time(hjg_ctx* ctx, double* total_ms, int32_t* launches) {
 }
 
 }  // extern "C"
+
+// ===================================================================== batched
+namespace {
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// Kernel specialisation of a problem's pair loop (problems that share it can
+// share a launch).
+struct SpecKey {
+  int datum, bucket, pairs, mfma, bf16;
+  bool operator<(const SpecKey& o) const {
+    return std::tie(datum, bucket, pairs, mfma, bf16) < std::tie(o.datum, o.bucket, o.pairs, o.mfma, o.bf16);
+  }
+};
+
+// Samples per split in a batched launch: the batch as a whole fills the GPU,
+// so each problem is cut only into splits of about this many samples.
+int batched_split_samples() {
+  int ns = 16384;
+  if (const char* e = std::getenv("HJG_BATCH_SPLIT")) ns = std::max(kBlk, std::atoi(e));
+  return ns / kBlk * kBlk;
+}
+
+}  // namespace
+
+extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* probs, const int64_t* q_off,
+                                        const int32_t* Ns, const int32_t* Ks, const double* ts, double tol,
+                                        const float* x_all, float* v_all, float* grad_all, double* resid_hist,
+                                        int32_t* iters, void* hip_stream) {
+  g_err.clear();
+  if (!ctx || !probs || !q_off || !Ns || !Ks || !ts) return fail(HJG_EINVAL, "NULL argument");
+  if (P < 1 || P > 65536) return fail(HJG_EINVAL, "P must be in [1, 65536]");
+  if (!std::isfinite(tol)) return fail(HJG_EINVAL, "tol must be finite");
+  if (q_off[0] != 0) return fail(HJG_EINVAL, "q_off[0] must be 0");
+  int Kmax = 0;
+  std::vector<int64_t> xo(P + 1, 0);
+  for (int p = 0; p < P; ++p) {
+    const int64_t Q = q_off[p + 1] - q_off[p];
+    int rc = check_common(ctx, &probs[p], Q, ts[p], Ns[p], 0);
+    if (rc) return fail(rc, "problem " + std::to_string(p) + ": " + g_err);
+    if (Q < 1) return fail(HJG_EINVAL, "problem " + std::to_string(p) + ": needs at least one state");
+    if (probs[p].sample_mode != HJG_S_CRN_STEP)
+      return fail(HJG_EUNSUPPORTED, "batched sweeps use common-random-number tables");
+    if (Ks[p] < 1 || Ks[p] > 255) return fail(HJG_EINVAL, "K must be in [1, 255]");
+    Kmax = std::max(Kmax, (int)Ks[p]);
+    xo[p + 1] = xo[p] + Q * probs[p].n;
+  }
+  if (!x_all || !v_all || !grad_all) return fail(HJG_EINVAL, "x_all, v_all and grad_all are required");
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto& B = ctx->batch;
+
+  // ---- key of this batch: every input the recorded graph depends on
+  std::vector<char> key;
+  auto put = [&](const void* d, size_t n) { key.insert(key.end(), (const char*)d, (const char*)d + n); };
+  put(&P, sizeof(P));
+  for (int p = 0; p < P; ++p) {
+    hjg_problem c;
+    copy_problem(&c, &probs[p]);
+    put(&c, sizeof(c));
+  }
+  put(q_off, sizeof(int64_t) * (P + 1));
+  put(Ns, sizeof(int32_t) * P);
+  put(Ks, sizeof(int32_t) * P);
+  put(ts, sizeof(double) * P);
+  put(&tol, sizeof(tol));
+  put(&x_all, sizeof(x_all));
+  put(&v_all, sizeof(v_all));
+  put(&grad_all, sizeof(grad_all));
+  const int split_ns = batched_split_samples();
+  put(&split_ns, sizeof(split_ns));
+
+  if (key != B.key || !B.exec) {
+    drop_batch_graph(ctx);
+    // ---- per-problem plan and workspace carving
+    struct Plan1 {
+      int64_t Q, qb_sweep, qb256;
+      int splits, ns, mfma, bf16;
+      int64_t tstride;
+      int64_t o_m, o_S, o_S2, o_G, o_vp, o_c, o_th, o_bp, o_res, o_ctrl, o_tab, o_zb;
+    };
+    std::vector<Plan1> pl(P);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+      const int64_t o = off;
+      off += align256(std::max<int64_t>(bytes, 8));
+      return o;
+    };
+    for (int p = 0; p < P; ++p) {
+      const hjg_problem& pr = probs[p];
+      Plan1& q = pl[p];
+      q.Q = q_off[p + 1] - q_off[p];
+      q.mfma = use_mfma(&pr);
+      q.bf16 = pr.sample_bf16 != 0;
+      const int qpb = q.mfma ? kQueriesPerBlockMfma : kQueriesPerBlockValu;
+      q.qb_sweep = div_up(q.Q, qpb);
+      q.qb256 = div_up(q.Q, kThreads);
+      q.ns = std::min<int64_t>(split_ns, div_up(Ns[p], kBlk) * kBlk);
+      q.splits = (int)div_up(Ns[p], q.ns);
+      q.tstride = div_up(Ns[p], 64) * 64;
+      const int64_t sq = (int64_t)q.splits * q.Q;
+      q.o_m = take(sq * 4);
+      q.o_S = take(sq * 8);
+      q.o_S2 = take(sq * 8);
+      q.o_G = take(sq * pr.n * 4);
+      q.o_vp = take(q.Q * 4);
+      q.o_c = take(q.Q * 4);
+      q.o_th = pr.tilt ? take(q.Q * pr.n * 4) : -1;
+      q.o_bp = take(q.qb256 * 16);
+      q.o_res = take(Ks[p] * 8);
+      q.o_ctrl = take(16);
+      q.o_tab = take((int64_t)pr.n * q.tstride * (q.bf16 ? 2 : 4));
+      q.o_zb = pr.grad_cv ? take(pr.n * 8) : -1;
+    }
+    int rc;
+    if ((rc = ensure(ctx, B.ws, off))) return rc;
+    char* ws = (char*)B.ws.p;
+    auto at = [&](int64_t o) -> void* { return o < 0 ? nullptr : (void*)(ws + o); };
+
+    // ---- argument records
+    std::vector<SweepArgs> sa(P);
+    std::vector<FinalizeArgs> fa(P);
+    std::vector<InitArgs> ia(P);
+    std::vector<ReduceArgs> ra(P);
+    B.resid_off.assign(P, 0);
+    B.ctrl_off.assign(P, 0);
+    B.K.assign(Ks, Ks + P);
+    for (int p = 0; p < P; ++p) {
+      const hjg_problem& pr = probs[p];
+      const Plan1& q = pl[p];
+      const float sigma = (float)std::sqrt(2.0 * pr.nu * ts[p]);
+      int* done = (int*)at(q.o_ctrl);
+      const Partials part{(float*)at(q.o_m), (double*)at(q.o_S), (double*)at(q.o_S2), (float*)at(q.o_G), nullptr};
+      float* th = (float*)at(q.o_th);
+      SweepArgs& A = sa[p];
+      A = SweepArgs{};
+      A.n = pr.n;
+      A.Q = q.Q;
+      A.N = Ns[p];
+      A.ns = q.ns;
+      A.splits = q.splits;
+      A.x = x_all + xo[p];
+      A.c = (const float*)at(q.o_c);
+      A.theta = th;
+      A.sigma = sigma;
+      A.table = at(q.o_tab);
+      A.tstride = q.tstride;
+      A.dp = datum_params(&pr);
+      A.k0 = (uint32_t)(pr.seed & 0xFFFFFFFFu);
+      A.k1 = (uint32_t)(pr.seed >> 32);
+      A.cv = pr.grad_cv;
+      A.mfma = q.mfma;
+      A.part = part;
+      A.done = done;
+      FinalizeArgs& F = fa[p];
+      F = FinalizeArgs{};
+      F.n = pr.n;
+      F.Q = q.Q;
+      F.N = Ns[p];
+      F.splits = q.splits;
+      F.sigma = sigma;
+      F.x = A.x;
+      F.c = A.c;
+      F.theta = th;
+      F.part = part;
+      F.cv = pr.grad_cv;
+      F.fresh = 0;
+      F.zbar_tab = (const double*)at(q.o_zb);
+      F.v = v_all + q_off[p];
+      F.grad = grad_all + xo[p];
+      F.ess = nullptr;
+      F.picard = 1;
+      F.vprev = (float*)at(q.o_vp);
+      F.tol = (float)tol;
+      F.vfloor = (float)(1e-2 * std::sqrt(2.0 * pr.nu * ts[p]) * std::sqrt((double)pr.n));
+      F.blockpart = (double*)at(q.o_bp);
+      F.c_next = (float*)at(q.o_c);
+      F.th_next = th;
+      F.hp = ham_params(&pr);
+      F.done = done;
+      InitArgs& I = ia[p];
+      I = InitArgs{};
+      I.n = pr.n;
+      I.Q = q.Q;
+      I.K = Ks[p];
+      I.sigma = sigma;
+      I.x = A.x;
+      I.dp = A.dp;
+      I.hp = F.hp;
+      I.tilt = pr.tilt;
+      I.vprev = F.vprev;
+      I.p = F.grad;
+      I.c = (float*)at(q.o_c);
+      I.th = th;
+      I.done = done;
+      I.iters = done + 1;
+      I.resid = (double*)at(q.o_res);
+      ReduceArgs& R = ra[p];
+      R = ReduceArgs{};
+      R.nblocks = (int)q.qb256;
+      R.blockpart = F.blockpart;
+      R.tol = (float)tol;
+      R.resid = I.resid;
+      R.done = done;
+      R.iters = done + 1;
+      B.resid_off[p] = q.o_res;
+      B.ctrl_off[p] = q.o_ctrl;
+    }
+    const int64_t o_sa = 0, o_fa = align256(P * sizeof(SweepArgs));
+    const int64_t o_ia = o_fa + align256(P * sizeof(FinalizeArgs));
+    const int64_t o_ra = o_ia + align256(P * sizeof(InitArgs));
+    const int64_t args_bytes = o_ra + align256(P * sizeof(ReduceArgs));
+    if ((rc = ensure(ctx, B.args, args_bytes))) return rc;
+    char* ab = (char*)B.args.p;
+    HJG_HIP(hipMemcpy(ab + o_sa, sa.data(), P * sizeof(SweepArgs), hipMemcpyHostToDevice));
+    HJG_HIP(hipMemcpy(ab + o_fa, fa.data(), P * sizeof(FinalizeArgs), hipMemcpyHostToDevice));
+    HJG_HIP(hipMemcpy(ab + o_ia, ia.data(), P * sizeof(InitArgs), hipMemcpyHostToDevice));
+    HJG_HIP(hipMemcpy(ab + o_ra, ra.data(), P * sizeof(ReduceArgs), hipMemcpyHostToDevice));
+    const SweepArgs* d_sa = (const SweepArgs*)(ab + o_sa);
+    const FinalizeArgs* d_fa = (const FinalizeArgs*)(ab + o_fa);
+    const InitArgs* d_ia = (const InitArgs*)(ab + o_ia);
+    const ReduceArgs* d_ra = (const ReduceArgs*)(ab + o_ra);
+
+    // ---- work items: init and finalize per register bucket, sweeps per
+    //      specialisation, heaviest items first; reduce lists per level
+    std::vector<int> items;   // int4 / int2 / int records, packed as ints
+    struct Launch {
+      int kind;     // 0 init, 1 sweep, 2 finalize, 3 reduce
+      int rep;      // representative problem (specialisation)
+      int64_t off;  // int offset in items
+      int count;
+      int level;
+    };
+    std::vector<Launch> launches;
+    auto bucket_of = [&](int p) { return n_bucket(probs[p].n); };
+    auto add_q_items = [&](int kind, int level) {
+      std::map<int, std::vector<int>> byb;
+      for (int p = 0; p < P; ++p)
+        if (kind == 0 || Ks[p] > level) byb[bucket_of(p)].push_back(p);
+      for (auto& kv : byb) {
+        while (items.size() % 2) items.push_back(0);   // int2 records: 8-byte aligned
+        const int64_t o = (int64_t)items.size();
+        int cnt = 0;
+        for (int p : kv.second)
+          for (int64_t b = 0; b < pl[p].qb256; ++b, ++cnt) {
+            items.push_back(p);
+            items.push_back((int)b);
+          }
+        launches.push_back(Launch{kind, kv.second[0], o, cnt, level});
+      }
+    };
+    add_q_items(0, 0);
+    for (int k = 0; k < Kmax; ++k) {
+      std::map<SpecKey, std::vector<int>> groups;
+      for (int p = 0; p < P; ++p) {
+        if (Ks[p] <= k) continue;
+        const hjg_problem& pr = probs[p];
+        const SpecKey sk{pr.datum, n_bucket(pr.n), pr.datum == HJG_L_MIN_PAIR_DISKS ? pr.n / 3 : 0, pl[p].mfma,
+                         pl[p].bf16};
+        groups[sk].push_back(p);
+      }
+      for (auto& kv : groups) {
+        struct It { int p, qb, sp; double cost; };
+        std::vector<It> its;
+        for (int p : kv.second)
+          for (int64_t qb = 0; qb < pl[p].qb_sweep; ++qb)
+            for (int sp = 0; sp < pl[p].splits; ++sp) {
+              const int samples = std::min<int64_t>(pl[p].ns, (int64_t)Ns[p] - (int64_t)sp * pl[p].ns);
+              its.push_back(It{p, (int)qb, sp, (double)samples * (probs[p].n + 10)});
+            }
+        std::stable_sort(its.begin(), its.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
+        while (items.size() % 4) items.push_back(0);     // int4 records: 16-byte aligned
+        const int64_t o = (int64_t)items.size();
+        for (const It& it : its) {
+          items.push_back(it.p);
+          items.push_back(it.qb);
+          items.push_back(it.sp);
+          items.push_back(0);
+        }
+        launches.push_back(Launch{1, kv.second[0], o, (int)its.size(), k});
+      }
+      add_q_items(2, k);
+      const int64_t o = (int64_t)items.size();
+      int cnt = 0;
+      for (int p = 0; p < P; ++p)
+        if (Ks[p] > k) {
+          items.push_back(p);
+          ++cnt;
+        }
+      launches.push_back(Launch{3, 0, o, cnt, k});
+    }
+    if ((rc = ensure(ctx, B.items, std::max<size_t>(items.size(), 4) * sizeof(int)))) return rc;
+    HJG_HIP(hipMemcpy(B.items.p, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+    const int* d_items = (const int*)B.items.p;
+
+    // ---- common tables (and their column means), generated once per plan
+    for (int p = 0; p < P; ++p) {
+      const hjg_problem& pr = probs[p];
+      const uint32_t k0 = (uint32_t)(pr.seed & 0xFFFFFFFFu), k1 = (uint32_t)(pr.seed >> 32);
+      HJG_HIP(launch_table(pr.n, pl[p].tstride, pl[p].tstride, k0, k1, make_tag(pr.problem_id, 0, 0), pl[p].bf16,
+                           at(pl[p].o_tab), s));
+      if (pr.grad_cv)
+        HJG_HIP(launch_zbar(pr.n, Ns[p], pl[p].tstride, pl[p].bf16, at(pl[p].o_tab), (double*)at(pl[p].o_zb), s));
+    }
+    HJG_HIP(hipStreamSynchronize(s));
+
+    // ---- record the whole uneven multi-problem Picard loop
+    HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (const Launch& L : launches) {
+      if (e != hipSuccess) break;
+      if (L.kind == 0) {
+        ItemBatch<InitArgs> b{d_ia, (const int2*)(d_items + L.off), L.count};
+        e = launch_init(ia[L.rep], ctx->cap, &b);
+      } else if (L.kind == 1) {
+        SweepBatch b{d_sa, (const int4*)(d_items + L.off), L.count};
+        e = launch_sweep(sa[L.rep], 0, pl[L.rep].bf16, ctx->cap, &b);
+      } else if (L.kind == 2) {
+        ItemBatch<FinalizeArgs> b{d_fa, (const int2*)(d_items + L.off), L.count};
+        e = launch_finalize(fa[L.rep], ctx->cap, &b);
+      } else {
+        e = launch_reduce_batched(d_ra, d_items + L.off, L.count, L.level, ctx->cap);
+      }
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(HJG_EHIP, std::string("batched graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(HJG_EHIP, std::string("batched graph instantiate: ") + hipGetErrorString(e3));
+    }
+    B.graph = graph;
+    B.exec = exec;
+    B.key = key;
+  }
+  HJG_HIP(hipGraphLaunch(B.exec, s));
+  if (resid_hist || iters) {
+    std::vector<double> r;
+    for (int p = 0; p < P; ++p) {
+      r.assign(B.K[p], 0.0);
+      int ctrl[2] = {0, 0};
+      HJG_HIP(hipMemcpyAsync(r.data(), (char*)B.ws.p + B.resid_off[p], B.K[p] * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      HJG_HIP(hipMemcpyAsync(ctrl, (char*)B.ws.p + B.ctrl_off[p], 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HJG_HIP(hipStreamSynchronize(s));
+      if (resid_hist)
+        for (int k = 0; k < Kmax; ++k) resid_hist[(int64_t)p * Kmax + k] = k < B.K[p] ? r[k] : 0.0;
+      if (iters) iters[p] = ctrl[1];
+    }
+  }
+  return HJG_OK;
+}

@@ -107,10 +107,28 @@ struct ReduceArgs {
   int* iters;
 };
 
-hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s);
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, hipStream_t s);
+// A batched launch: block b serves items[b] = (problem, query block, split)
+// with probs[problem]; every problem of one launch shares the kernel
+// specialisation of the SweepArgs passed alongside.
+struct SweepBatch {
+  const SweepArgs* probs;
+  const int4* items;
+  int count;
+};
+
+hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b = nullptr);
+// A batched per-query launch: block b serves items[b] = (problem, query block).
+template <class Args>
+struct ItemBatch {
+  const Args* args;
+  const int2* items;
+  int count;
+};
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s, const ItemBatch<FinalizeArgs>* b = nullptr);
+hipError_t launch_init(const InitArgs& a, hipStream_t s, const ItemBatch<InitArgs>* b = nullptr);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_reduce_batched(const ReduceArgs* args, const int* plist, int count, int k, hipStream_t s);
 hipError_t launch_table(int n, int64_t limit, int64_t tstride, uint32_t k0, uint32_t k1, uint32_t tag, int bf16,
                         void* out, hipStream_t s);
 hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s);

@@ -7,19 +7,19 @@
 
 namespace hjg {
 
-hipError_t launch_sweep_half_sqnorm(const SweepArgs&, int, int, hipStream_t);
-hipError_t launch_sweep_ball(const SweepArgs&, int, int, hipStream_t);
-hipError_t launch_sweep_min_pair_disks(const SweepArgs&, int, int, hipStream_t);
-hipError_t launch_sweep_knn_balls(const SweepArgs&, int, int, hipStream_t);
-hipError_t launch_sweep_linear(const SweepArgs&, int, int, hipStream_t);
+hipError_t launch_sweep_half_sqnorm(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
+hipError_t launch_sweep_ball(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
+hipError_t launch_sweep_min_pair_disks(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
+hipError_t launch_sweep_knn_balls(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
+hipError_t launch_sweep_linear(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
 
-hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
   switch (a.dp.kind) {
-    case HJG_L_HALF_SQNORM: return launch_sweep_half_sqnorm(a, fresh, bf16, s);
-    case HJG_L_BALL: return launch_sweep_ball(a, fresh, bf16, s);
-    case HJG_L_MIN_PAIR_DISKS: return launch_sweep_min_pair_disks(a, fresh, bf16, s);
-    case HJG_L_KNN_BALLS: return launch_sweep_knn_balls(a, fresh, bf16, s);
-    case HJG_L_LINEAR: return launch_sweep_linear(a, fresh, bf16, s);
+    case HJG_L_HALF_SQNORM: return launch_sweep_half_sqnorm(a, fresh, bf16, s, b);
+    case HJG_L_BALL: return launch_sweep_ball(a, fresh, bf16, s, b);
+    case HJG_L_MIN_PAIR_DISKS: return launch_sweep_min_pair_disks(a, fresh, bf16, s, b);
+    case HJG_L_KNN_BALLS: return launch_sweep_knn_balls(a, fresh, bf16, s, b);
+    case HJG_L_LINEAR: return launch_sweep_linear(a, fresh, bf16, s, b);
     default: return hipErrorInvalidValue;
   }
 }
@@ -93,12 +93,12 @@ __global__ __launch_bounds__(kThreads) void finite_kernel(const float* a, int64_
 
 // ------------------------------------------------------------ Picard start
 template <int NM>
-__global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) {
-  if (blockIdx.x == 0) {
+__device__ __forceinline__ void init_block(const InitArgs& I, int64_t qblock) {
+  if (qblock == 0) {
     for (int k = threadIdx.x; k < I.K; k += kThreads) I.resid[k] = 0.0;
     if (threadIdx.x == 0) { *I.done = 0; *I.iters = 0; }
   }
-  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t q = qblock * kThreads + threadIdx.x;
   if (q >= I.Q) return;
   float x[NM], g[NM];
 #pragma unroll
@@ -120,6 +120,16 @@ __global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) {
   }
 }
 
+template <int NM>
+__global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) { init_block<NM>(I, blockIdx.x); }
+
+template <int NM>
+__global__ __launch_bounds__(kThreads) void init_batched_kernel(const InitArgs* args, const int2* items) {
+  const int2 it = items[blockIdx.x];
+  const InitArgs I = args[it.x];
+  init_block<NM>(I, it.y);
+}
+
 // ------------------------------------------------------------ finalize
 // Merge the split partials in float64 (max-rescaled sums), then
 //   v = -(m ln 2 + ln(S/N)) / c,  Dv = -(theta + sigma (G/S - [zbar])) / (c sigma^2),
@@ -127,9 +137,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(InitArgs I) {
 // and, inside the Picard loop, the residual terms, the per-query flag and the
 // next coefficient and shift from p = Dv.
 template <int NM>
-__global__ __launch_bounds__(kThreads) void finalize_kernel(FinalizeArgs F) {
-  if (F.done && *F.done) return;
-  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qblock) {
+  const int64_t q = qblock * kThreads + threadIdx.x;
   const bool active = q < F.Q;
   double dv2 = 0.0, vp2 = 0.0;
   if (active) {
@@ -199,15 +208,28 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(FinalizeArgs F) {
     if (threadIdx.x == 0) {
       double a = 0.0, b = 0.0;
       for (int w = 0; w < kThreads / 64; ++w) { a += red[0][w]; b += red[1][w]; }
-      F.blockpart[2 * blockIdx.x] = a;
-      F.blockpart[2 * blockIdx.x + 1] = b;
+      F.blockpart[2 * qblock] = a;
+      F.blockpart[2 * qblock + 1] = b;
     }
   }
 }
 
+template <int NM>
+__global__ __launch_bounds__(kThreads) void finalize_kernel(FinalizeArgs F) {
+  if (F.done && *F.done) return;
+  finalize_block<NM>(F, blockIdx.x);
+}
+
+template <int NM>
+__global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const FinalizeArgs* args, const int2* items) {
+  const int2 it = items[blockIdx.x];
+  const FinalizeArgs F = args[it.x];
+  if (F.done && *F.done) return;
+  finalize_block<NM>(F, it.y);
+}
+
 // Relative L2 change over all queries from the block partials (float64, fixed order).
-__global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs R) {
-  if (*R.done) return;
+__device__ __forceinline__ void reduce_block(const ReduceArgs& R) {
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < R.nblocks; i += kThreads) { a += R.blockpart[2 * i]; b += R.blockpart[2 * i + 1]; }
   __shared__ double ra[kThreads], rb[kThreads];
@@ -225,6 +247,19 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs R) {
     *R.iters = R.k + 1;
     if (r < (double)R.tol) *R.done = 1;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs R) {
+  if (*R.done) return;
+  reduce_block(R);
+}
+
+// One block per problem of the list; k overrides the level.
+__global__ __launch_bounds__(kThreads) void reduce_batched_kernel(const ReduceArgs* args, const int* plist, int k) {
+  ReduceArgs R = args[plist[blockIdx.x]];
+  if (*R.done) return;
+  R.k = k;
+  reduce_block(R);
 }
 
 }  // namespace
@@ -255,32 +290,55 @@ hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_init(const InitArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)std::max<int64_t>((a.Q + kThreads - 1) / kThreads, 1));
+template <int NM>
+void init_launch(const InitArgs& a, hipStream_t s, const ItemBatch<InitArgs>* b) {
+  if (b) {
+    init_batched_kernel<NM><<<b->count, kThreads, 0, s>>>(b->args, b->items);
+  } else {
+    const dim3 grid((unsigned)std::max<int64_t>((a.Q + kThreads - 1) / kThreads, 1));
+    init_kernel<NM><<<grid, kThreads, 0, s>>>(a);
+  }
+}
+
+template <int NM>
+void finalize_launch(const FinalizeArgs& a, hipStream_t s, const ItemBatch<FinalizeArgs>* b) {
+  if (b) {
+    finalize_batched_kernel<NM><<<b->count, kThreads, 0, s>>>(b->args, b->items);
+  } else {
+    const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads));
+    finalize_kernel<NM><<<grid, kThreads, 0, s>>>(a);
+  }
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s, const ItemBatch<InitArgs>* b) {
   switch (n_bucket(a.n)) {
-    case 4: init_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
-    case 8: init_kernel<8><<<grid, kThreads, 0, s>>>(a); break;
-    case 16: init_kernel<16><<<grid, kThreads, 0, s>>>(a); break;
-    case 32: init_kernel<32><<<grid, kThreads, 0, s>>>(a); break;
-    default: init_kernel<48><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: init_launch<4>(a, s, b); break;
+    case 8: init_launch<8>(a, s, b); break;
+    case 16: init_launch<16>(a, s, b); break;
+    case 32: init_launch<32>(a, s, b); break;
+    default: init_launch<48>(a, s, b); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads));
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s, const ItemBatch<FinalizeArgs>* b) {
   switch (n_bucket(a.n)) {
-    case 4: finalize_kernel<4><<<grid, kThreads, 0, s>>>(a); break;
-    case 8: finalize_kernel<8><<<grid, kThreads, 0, s>>>(a); break;
-    case 16: finalize_kernel<16><<<grid, kThreads, 0, s>>>(a); break;
-    case 32: finalize_kernel<32><<<grid, kThreads, 0, s>>>(a); break;
-    default: finalize_kernel<48><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: finalize_launch<4>(a, s, b); break;
+    case 8: finalize_launch<8>(a, s, b); break;
+    case 16: finalize_launch<16>(a, s, b); break;
+    case 32: finalize_launch<32>(a, s, b); break;
+    default: finalize_launch<48>(a, s, b); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   reduce_kernel<<<1, kThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(const ReduceArgs* args, const int* plist, int count, int k, hipStream_t s) {
+  reduce_batched_kernel<<<count, kThreads, 0, s>>>(args, plist, k);
   return hipGetLastError();
 }
 

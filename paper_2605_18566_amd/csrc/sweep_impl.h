@@ -207,14 +207,13 @@ __device__ __forceinline__ void write_partials(const SweepArgs& A, const LseAcc<
 }
 
 // ------------------------------------------------------------ common table (CRN)
+// One block of the pair loop: queries qblock*256 .. +255, sample split `split`.
 template <int DATUM, int NM, int MP, bool BF16>
-__global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
-  if (A.done && *A.done) return;
+__device__ __forceinline__ void sweep_crn_block(const SweepArgs& A, int64_t qblock, int split) {
   __shared__ float zs[NM][kBlk];
-  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t q = qblock * kThreads + threadIdx.x;
   const bool active = q < A.Q;
   const int64_t qs = active ? q : A.Q - 1;   // a valid state to read for idle lanes
-  const int split = blockIdx.y;
   const int i_begin = split * A.ns;
   const int i_end = min(A.N, i_begin + A.ns);
 
@@ -263,6 +262,22 @@ __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
     __syncthreads();
   }
   if (active) write_partials<NM>(A, L, q, split, false);
+}
+
+template <int DATUM, int NM, int MP, bool BF16>
+__global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
+  if (A.done && *A.done) return;
+  sweep_crn_block<DATUM, NM, MP, BF16>(A, blockIdx.x, blockIdx.y);
+}
+
+// Many problems in one launch: block b serves work item items[b] =
+// (problem, query block, sample split) with that problem's arguments.
+template <int DATUM, int NM, int MP, bool BF16>
+__global__ __launch_bounds__(kThreads) void sweep_crn_batched_kernel(const SweepArgs* probs, const int4* items) {
+  const int4 it = items[blockIdx.x];
+  const SweepArgs A = probs[it.x];
+  if (A.done && *A.done) return;
+  sweep_crn_block<DATUM, NM, MP, BF16>(A, it.y, it.z);
 }
 
 // ------------------------------------------------------------------ fresh draws
@@ -324,16 +339,26 @@ __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
 }
 
 template <int DATUM, int NM, int MP>
-hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
   if (a.mfma) {
     if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
       if (fresh || !bf16) return hipErrorInvalidValue;
-      const dim3 grid((unsigned)((a.Q + kMQ - 1) / kMQ), (unsigned)a.splits);
-      sweep_mfma_kernel<DATUM, NM, MP><<<grid, 256, 0, s>>>(a);
+      if (b) {
+        sweep_mfma_batched_kernel<DATUM, NM, MP><<<b->count, 256, 0, s>>>(b->probs, b->items);
+      } else {
+        const dim3 grid((unsigned)((a.Q + kMQ - 1) / kMQ), (unsigned)a.splits);
+        sweep_mfma_kernel<DATUM, NM, MP><<<grid, 256, 0, s>>>(a);
+      }
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
+  }
+  if (b) {
+    if (fresh) return hipErrorInvalidValue;
+    if (bf16) sweep_crn_batched_kernel<DATUM, NM, MP, true><<<b->count, kThreads, 0, s>>>(b->probs, b->items);
+    else sweep_crn_batched_kernel<DATUM, NM, MP, false><<<b->count, kThreads, 0, s>>>(b->probs, b->items);
+    return hipGetLastError();
   }
   const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads), (unsigned)a.splits);
   if (fresh) {
@@ -353,40 +378,40 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
 // Disc pairs: the exact pair count as a template argument for the sizes the
 // workloads use, otherwise the bucket's NM/3 pairs with padded pairs far away.
 template <int NM, int M>
-hipError_t launch_pairs_exact(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
-  return launch_sweep_dn<HJG_L_MIN_PAIR_DISKS, NM, M>(a, fresh, bf16, s);
+hipError_t launch_pairs_exact(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
+  return launch_sweep_dn<HJG_L_MIN_PAIR_DISKS, NM, M>(a, fresh, bf16, s, b);
 }
 
 template <int DATUM>
-hipError_t launch_sweep_d(const SweepArgs& a, int fresh, int bf16, hipStream_t s) {
+hipError_t launch_sweep_d(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
   if constexpr (DATUM == HJG_L_KNN_BALLS) {
-    return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s);
+    return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s, b);
   } else if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
     switch (a.n / 3) {
-      case 1: return launch_pairs_exact<4, 1>(a, fresh, bf16, s);
-      case 2: return launch_pairs_exact<8, 2>(a, fresh, bf16, s);
-      case 3: return launch_pairs_exact<16, 3>(a, fresh, bf16, s);
-      case 4: return launch_pairs_exact<16, 4>(a, fresh, bf16, s);
-      case 5: return launch_pairs_exact<16, 5>(a, fresh, bf16, s);
-      case 6: return launch_pairs_exact<32, 6>(a, fresh, bf16, s);
-      case 7: return launch_pairs_exact<32, 7>(a, fresh, bf16, s);
-      case 8: return launch_pairs_exact<32, 8>(a, fresh, bf16, s);
-      case 9: return launch_pairs_exact<32, 9>(a, fresh, bf16, s);
-      case 10: return launch_pairs_exact<32, 10>(a, fresh, bf16, s);
-      case 11: return launch_pairs_exact<48, 11>(a, fresh, bf16, s);
-      case 12: return launch_pairs_exact<48, 12>(a, fresh, bf16, s);
-      case 13: return launch_pairs_exact<48, 13>(a, fresh, bf16, s);
-      case 14: return launch_pairs_exact<48, 14>(a, fresh, bf16, s);
-      case 15: return launch_pairs_exact<48, 15>(a, fresh, bf16, s);
-      default: return launch_pairs_exact<48, 16>(a, fresh, bf16, s);
+      case 1: return launch_pairs_exact<4, 1>(a, fresh, bf16, s, b);
+      case 2: return launch_pairs_exact<8, 2>(a, fresh, bf16, s, b);
+      case 3: return launch_pairs_exact<16, 3>(a, fresh, bf16, s, b);
+      case 4: return launch_pairs_exact<16, 4>(a, fresh, bf16, s, b);
+      case 5: return launch_pairs_exact<16, 5>(a, fresh, bf16, s, b);
+      case 6: return launch_pairs_exact<32, 6>(a, fresh, bf16, s, b);
+      case 7: return launch_pairs_exact<32, 7>(a, fresh, bf16, s, b);
+      case 8: return launch_pairs_exact<32, 8>(a, fresh, bf16, s, b);
+      case 9: return launch_pairs_exact<32, 9>(a, fresh, bf16, s, b);
+      case 10: return launch_pairs_exact<32, 10>(a, fresh, bf16, s, b);
+      case 11: return launch_pairs_exact<48, 11>(a, fresh, bf16, s, b);
+      case 12: return launch_pairs_exact<48, 12>(a, fresh, bf16, s, b);
+      case 13: return launch_pairs_exact<48, 13>(a, fresh, bf16, s, b);
+      case 14: return launch_pairs_exact<48, 14>(a, fresh, bf16, s, b);
+      case 15: return launch_pairs_exact<48, 15>(a, fresh, bf16, s, b);
+      default: return launch_pairs_exact<48, 16>(a, fresh, bf16, s, b);
     }
   } else {
     switch (n_bucket(a.n)) {
-      case 4: return launch_sweep_dn<DATUM, 4, 0>(a, fresh, bf16, s);
-      case 8: return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s);
-      case 16: return launch_sweep_dn<DATUM, 16, 0>(a, fresh, bf16, s);
-      case 32: return launch_sweep_dn<DATUM, 32, 0>(a, fresh, bf16, s);
-      default: return launch_sweep_dn<DATUM, 48, 0>(a, fresh, bf16, s);
+      case 4: return launch_sweep_dn<DATUM, 4, 0>(a, fresh, bf16, s, b);
+      case 8: return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s, b);
+      case 16: return launch_sweep_dn<DATUM, 16, 0>(a, fresh, bf16, s, b);
+      case 32: return launch_sweep_dn<DATUM, 32, 0>(a, fresh, bf16, s, b);
+      default: return launch_sweep_dn<DATUM, 48, 0>(a, fresh, bf16, s, b);
     }
   }
 }

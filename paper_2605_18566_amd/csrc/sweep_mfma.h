@@ -99,8 +99,7 @@ __device__ __forceinline__ float mfma_ell(const float* ud, const float* sd, floa
 }
 
 template <int DATUM, int NM, int MP>
-__global__ __launch_bounds__(256) void sweep_mfma_kernel(SweepArgs A) {
-  if (A.done && *A.done) return;
+__device__ __forceinline__ void sweep_mfma_block(const SweepArgs& A, int64_t qblock, int split) {
   constexpr int KS = NM / 16;              // K steps of the tilt product
   constexpr int GT = (NM + 31) / 32;       // 32-dimension tiles of G^T
   constexpr int ND = mfma_ndat<DATUM, NM, MP>();
@@ -111,10 +110,9 @@ __global__ __launch_bounds__(256) void sweep_mfma_kernel(SweepArgs A) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int ql = lane & 31, h = lane >> 5;
-  const int64_t q = (int64_t)blockIdx.x * kMQ + wave * 32 + ql;
+  const int64_t q = qblock * kMQ + wave * 32 + ql;
   const bool active = q < A.Q;
   const int64_t qs = active ? q : A.Q - 1;
-  const int split = blockIdx.y;
   const int i_begin = split * A.ns;
   const int i_end = min(A.N, i_begin + A.ns);
   const bool use_t = (A.theta != nullptr) || DATUM == HJG_L_LINEAR;
@@ -310,6 +308,20 @@ __global__ __launch_bounds__(256) void sweep_mfma_kernel(SweepArgs A) {
         if (dim < A.n) A.part.G[((int64_t)split * A.n + dim) * A.Q + q] = G[t][v];
       }
   }
+}
+
+template <int DATUM, int NM, int MP>
+__global__ __launch_bounds__(256) void sweep_mfma_kernel(SweepArgs A) {
+  if (A.done && *A.done) return;
+  sweep_mfma_block<DATUM, NM, MP>(A, blockIdx.x, blockIdx.y);
+}
+
+template <int DATUM, int NM, int MP>
+__global__ __launch_bounds__(256) void sweep_mfma_batched_kernel(const SweepArgs* probs, const int4* items) {
+  const int4 it = items[blockIdx.x];
+  const SweepArgs A = probs[it.x];
+  if (A.done && *A.done) return;
+  sweep_mfma_block<DATUM, NM, MP>(A, it.y, it.z);
 }
 
 }  // namespace hjg

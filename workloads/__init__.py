@@ -109,3 +109,36 @@ C5Q = replace(C5, name="c5q_quadratic15_n45", ham="quadratic", tube=False, cfg=6
 def horizons(w: Workload):
     """Time-to-go of each horizon: t_j = j T / S_t, j = 1..S_t."""
     return [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
+
+
+# 256 problems of stacked decoupled Dubins pairs (n = 3m, m ~ U{1..16}),
+# N log-uniform in [4,096, 262,144] and Q log-uniform in [1,024, 65,536]
+# (multiples of 256), nu log-uniform in [1e-3, 1e-1], K ~ U{3..8}, t = 1,
+# bfloat16 common draws, tube coefficient, Laplace shift.
+@dataclass
+class BatchProblem:
+    w: Workload
+    problem_id: int
+
+
+def c3_batch(P: int = 256, scale: float = 1.0, trial: int = 0):
+    """The uneven batch; `scale` < 1 shrinks N and Q (for tests), keeping the spread."""
+    g = rng(3, trial)
+    out = []
+    for p in range(P):
+        m = int(g.integers(1, 17))
+        N = int(np.exp(g.uniform(np.log(4096), np.log(262144))) * scale) // 256 * 256
+        Q = int(np.exp(g.uniform(np.log(1024), np.log(65536))) * scale) // 256 * 256
+        nu = float(np.exp(g.uniform(np.log(1e-3), np.log(1e-1))))
+        K = int(g.integers(3, 9))
+        w = Workload(f"c3_p{p}", n=3 * m, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=nu, t=1.0,
+                     Q=max(Q, 256), N=max(N, 256), K=K, box=dubins_box(m), tilt=True, sample_mode="crn_step",
+                     sample_bf16=True, cfg=3, tube=True)
+        out.append(BatchProblem(w, p))
+    return out
+
+
+def c3_fields(bp: BatchProblem) -> dict:
+    f = bp.w.problem_fields()
+    f["seed"] = philox_seed(3) + 1000 * bp.problem_id
+    return f
