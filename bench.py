@@ -10,8 +10,9 @@ Q * N * K / (seconds per step).
 Prints one JSON line with the throughput, the roofline of the dominant kernel
 (the pair loop, timed by HIP events around every launch inside the timed
 region), the FP64 CPU oracle timed on a bounded sample of the same workload,
-the estimator's health on that workload (ESS, Picard residuals) and the
-surrogate-vs-plain study at equal RMS value error.
+the estimator's health on that workload (ESS, Picard residuals), the
+surrogate-vs-plain study at equal RMS value error and the uneven-batch study
+(one batched graph vs one call per problem).
 """
 from __future__ import annotations
 
@@ -161,6 +162,69 @@ def surrogate_study(ctx, stream):
             "speedup_at_equal_rms": speedup}
 
 
+def batched_study(ctx, stream, P: int = 256):
+    """The uneven batch (stacked Dubins pairs, n = 3..48, N and Q log-uniform,
+    K = 3..8): one call per problem vs one batched call (one recorded graph),
+    before and after the autotuner picks the samples per split."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, autotune_batched, picard_sweep, picard_sweep_batched
+    batch = workloads.c3_batch(P=P)
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(np.ascontiguousarray(workloads.queries(bp.w, trial=1 + i).T)).to(dev)
+          for i, bp in enumerate(batch)]
+    specs = []
+    for bp in batch:
+        f = workloads.c3_fields(bp)
+        specs.append(ProblemSpec(problem_id=bp.problem_id, **f))
+    N = [bp.w.N for bp in batch]
+    K = [bp.w.K for bp in batch]
+    t = [bp.w.t for bp in batch]
+    pairs = float(sum(bp.w.Q * bp.w.N * bp.w.K for bp in batch))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    with torch.cuda.stream(stream):
+        def one_by_one():
+            for p in range(P):
+                picard_sweep(ctx, specs[p], xs[p], t[p], N[p], K[p], host_outputs=False, stream=stream)
+        one_by_one()                                            # records the per-problem graphs
+        dt_one, _ = timed(one_by_one)
+        print(f"batched study: one call per problem {dt_one:.3f} s", file=sys.stderr, flush=True)
+
+        def batched():
+            return picard_sweep_batched(ctx, specs, xs, N, K, t, host_outputs=False, stream=stream)
+        batched()                                               # records the batched graph
+        dt_b, _ = timed(batched)
+        print(f"batched study: one batched call {dt_b:.3f} s", file=sys.stderr, flush=True)
+        split, _ = autotune_batched(ctx, specs, xs, N, K, t, stream=stream)
+        batched()
+        dt_t, out = timed(batched)
+        print(f"batched study: tuned split {split}: {dt_t:.3f} s", file=sys.stderr, flush=True)
+    v = out.v.cpu().numpy()
+    if not np.all(np.isfinite(v)):
+        raise RuntimeError("non-finite values in the batched study")
+    ns = [bp.w.n for bp in batch]
+    slots = float(sum(bp.w.Q * bp.w.N * bp.w.K * alu_slots_per_pair(bp.w.datum, bp.w.n) for bp in batch))
+    return {"workload": f"{P} uneven problems: n = 3m, m ~ U{{1..16}} (n {min(ns)}..{max(ns)}), "
+                        "N log-U[4096, 262144], Q log-U[1024, 65536], nu log-U[1e-3, 1e-1], K ~ U{3..8}, "
+                        "bf16 common draws, tube coefficient, Laplace shift",
+            "pairs": pairs,
+            "one_call_per_problem": {"seconds": dt_one, "query_samples_per_s": pairs / dt_one},
+            "batched_default_split": {"seconds": dt_b, "query_samples_per_s": pairs / dt_b},
+            "batched_autotuned": {"samples_per_split": split, "seconds": dt_t, "query_samples_per_s": pairs / dt_t},
+            "speedup_batched_vs_one_by_one": dt_one / dt_t,
+            "alu_frac_whole_call": slots / dt_t / VALU_PEAK,
+            "one_call_per_problem_includes": "per-call table generation and graph recording (16-graph cache)"}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -195,6 +259,7 @@ def main():
     ap.add_argument("--queries", type=int, default=None, help="override Q (default: the workload's 262,144)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the equal-accuracy surrogate study")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -267,6 +332,9 @@ def main():
     study = None
     if not args.no_surrogate:
         study = surrogate_study(ctx, stream)
+    bstudy = None
+    if not args.no_batched:
+        bstudy = batched_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -300,6 +368,7 @@ def main():
         "cpu_baseline": cpu,
         "estimator_health": health,
         "surrogate": study,
+        "batched": bstudy,
     }
     print(json.dumps(line))
 

@@ -232,6 +232,31 @@ int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problem
                              int32_t* iters, void* hip_stream);
 
 /*
+ * Autotuner.  The pair loop cuts each state's N draws into sample splits so a
+ * launch has enough blocks; the split granularity is tuned per kernel
+ * specialisation and size bucket (log2 Q, log2 N).
+ * hjg_autotune_sweep times hjg_value_grad (HIP events, mean of 3 after one
+ * warm-up) at the given arguments for targets of 512 .. 16384 blocks and keeps
+ * the fastest in the context's tuning table (used by later hjg_value_grad and
+ * hjg_picard_sweep calls in the same bucket); *best_blocks and *best_ms
+ * receive the choice.  hjg_autotune_batched does the same for the samples per
+ * split of hjg_picard_sweep_batched (4096 .. 65536), running the given batch.
+ * Both synchronise the stream.  hjg_tuning_save / hjg_tuning_load write and
+ * read the table as text ("hjg-tuning gfx950 1", then "key = value" lines);
+ * load replaces the table, and rejects files of another format.
+ */
+int hjg_autotune_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q, const float* x,
+                       double t, int32_t N, const float* c, const float* theta,
+                       int32_t* best_blocks, double* best_ms, void* hip_stream);
+int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problems,
+                         const int64_t* q_off, const int32_t* N, const int32_t* K,
+                         const double* t, double tol, const float* x_all, float* v_all,
+                         float* grad_all, int32_t* best_split, double* best_ms,
+                         void* hip_stream);
+int hjg_tuning_save(const hjg_ctx* ctx, const char* path);
+int hjg_tuning_load(hjg_ctx* ctx, const char* path);
+
+/*
  * ------------------------------------------------------------------------
  * Learned surrogate (x, t) -> (v, Dv).
  *

@@ -81,6 +81,15 @@ SIGNATURES = [
                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                            C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                            C.POINTER(C.c_int32), C.c_void_p]),
+    ("hjg_autotune_sweep", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double,
+                                     C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double), C.c_void_p]),
+    ("hjg_autotune_batched", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.c_void_p]),
+    ("hjg_tuning_save", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("hjg_tuning_load", C.c_int, [C.c_void_p, C.c_char_p]),
     ("hjg_surrogate_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                        C.POINTER(C.c_void_p)]),
     ("hjg_surrogate_destroy", None, [C.c_void_p]),

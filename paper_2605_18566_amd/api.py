@@ -106,6 +106,12 @@ class Context:
         check(_lib.lib().hjg_sweep_time(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def save_tuning(self, path: str):
+        check(_lib.lib().hjg_tuning_save(self._h, str(path).encode()))
+
+    def load_tuning(self, path: str):
+        check(_lib.lib().hjg_tuning_load(self._h, str(path).encode()))
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().hjg_ctx_destroy(self._h)
@@ -255,6 +261,40 @@ def picard_sweep_batched(ctx: Context, specs, xs, N, K, t, tol: float = 0.0, hos
         out.resid_hist = np.array(list(hist)).reshape(P, max(K))
         out.iters = np.array(list(it), dtype=np.int32)
     return out
+
+
+def autotune_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, c: torch.Tensor,
+                   theta: Optional[torch.Tensor] = None, stream=None):
+    """Tune the sample-split target of this sweep's bucket; returns (blocks, ms)."""
+    _require_cuda(x, "x")
+    _require_cuda(c, "c")
+    n, Q = x.shape
+    b, ms = C.c_int32(0), C.c_double(0.0)
+    p = spec.to_c()
+    check(_lib.lib().hjg_autotune_sweep(ctx.handle, C.byref(p), Q, _ptr(x), float(t), int(N), _ptr(c),
+                                        _ptr(theta), C.byref(b), C.byref(ms), _stream(stream)))
+    return int(b.value), float(ms.value)
+
+
+def autotune_batched(ctx: Context, specs, xs, N, K, t, tol: float = 0.0, stream=None):
+    """Tune the samples per split of the batched sweep on this batch; returns (split, ms)."""
+    P = len(specs)
+    x_all = torch.cat([x.reshape(-1) for x in xs]).contiguous()
+    Qs = [x.shape[1] for x in xs]
+    q_off = np.zeros(P + 1, dtype=np.int64)
+    q_off[1:] = np.cumsum(Qs)
+    nx = sum(s.n * q for s, q in zip(specs, Qs))
+    v = torch.empty(int(q_off[-1]), dtype=torch.float32, device=x_all.device)
+    g = torch.empty(nx, dtype=torch.float32, device=x_all.device)
+    probs = (_lib.Problem * P)(*[s.to_c() for s in specs])
+    qo = (C.c_int64 * (P + 1))(*q_off.tolist())
+    Na = (C.c_int32 * P)(*[int(v) for v in N])
+    Ka = (C.c_int32 * P)(*[int(v) for v in K])
+    ta = (C.c_double * P)(*[float(v) for v in t])
+    b, ms = C.c_int32(0), C.c_double(0.0)
+    check(_lib.lib().hjg_autotune_batched(ctx.handle, P, probs, qo, Na, Ka, ta, float(tol), _ptr(x_all), _ptr(v),
+                                          _ptr(g), C.byref(b), C.byref(ms), _stream(stream)))
+    return int(b.value), float(ms.value)
 
 
 # ----------------------------------------------------------------- surrogate

@@ -9,6 +9,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <fstream>
+#include <sstream>
 #include <vector>
 
 #include "hjg.h"
@@ -63,6 +65,8 @@ struct hjg_ctx {
   int timing = 0;
   std::vector<hipEvent_t> ev;   // [2 * kMaxTimed]: begin/end per sweep launch
   int last_pairs = 0;           // event pairs used by the last call
+  // tuning table: sample-split targets chosen by the autotuner
+  std::map<std::string, int> tuning;
   // the last batched plan (workspace, argument records, work items, graph)
   struct BatchPlan {
     std::vector<char> key;
@@ -228,8 +232,23 @@ struct Plan {
 
 // Cut the N samples of each query into contiguous splits so that the launch
 // has enough blocks to fill 256 CUs (about 8 resident blocks each).
-Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block) {
-  int target = 2048;
+int ilog2(int64_t v) {
+  int l = 0;
+  while (v > 1) { v >>= 1; ++l; }
+  return l;
+}
+
+// Tuning-table key of a single-problem sweep: kernel specialisation and size bucket.
+std::string sweep_key(const hjg_problem* p, int64_t Q, int N) {
+  std::ostringstream k;
+  k << "sweep " << (use_mfma(p) ? 1 : 0) << ' ' << p->datum << ' ' << n_bucket(p->n) << ' '
+    << (p->datum == HJG_L_MIN_PAIR_DISKS ? p->n / 3 : 0) << ' ' << p->sample_mode << ' ' << p->sample_bf16 << ' '
+    << ilog2(Q) << ' ' << ilog2(N);
+  return k.str();
+}
+
+Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block, int tuned = 0) {
+  int target = tuned > 0 ? tuned : 2048;
   if (const char* e = std::getenv("HJG_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
   const int64_t qblocks = div_up(Q, queries_per_block);
   const int gran = fresh ? 64 : kBlk;
@@ -386,7 +405,9 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const bool mf = use_mfma(p);
-  const Plan pl = plan_splits(Q, N, fresh, mf ? kQueriesPerBlockMfma : kQueriesPerBlockValu);
+  const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
+  const Plan pl = plan_splits(Q, N, fresh, mf ? kQueriesPerBlockMfma : kQueriesPerBlockValu,
+                              tv == ctx->tuning.end() ? 0 : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
   const float sigma = (float)std::sqrt(2.0 * p->nu * t);
@@ -616,7 +637,9 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   HJG_HIP(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
-  const Plan pl = plan_splits(Q, N, fresh, use_mfma(p) ? kQueriesPerBlockMfma : kQueriesPerBlockValu);
+  const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
+  const Plan pl = plan_splits(Q, N, fresh, use_mfma(p) ? kQueriesPerBlockMfma : kQueriesPerBlockValu,
+                              tv == ctx->tuning.end() ? 0 : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
@@ -753,9 +776,12 @@ struct SpecKey {
 
 // Samples per split in a batched launch: the batch as a whole fills the GPU,
 // so each problem is cut only into splits of about this many samples.
-int batched_split_samples() {
+int batched_split_samples(const hjg_ctx* ctx) {
   int ns = 16384;
-  if (const char* e = std::getenv("HJG_BATCH_SPLIT")) ns = std::max(kBlk, std::atoi(e));
+  const auto it = ctx->tuning.find("batch");
+  if (it != ctx->tuning.end()) ns = it->second;
+  if (const char* e = std::getenv("HJG_BATCH_SPLIT")) ns = std::atoi(e);
+  ns = std::max(ns, kBlk);
   return ns / kBlk * kBlk;
 }
 
@@ -805,7 +831,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
   put(&x_all, sizeof(x_all));
   put(&v_all, sizeof(v_all));
   put(&grad_all, sizeof(grad_all));
-  const int split_ns = batched_split_samples();
+  const int split_ns = batched_split_samples(ctx);
   put(&split_ns, sizeof(split_ns));
 
   if (key != B.key || !B.exec) {
@@ -1091,5 +1117,143 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       if (iters) iters[p] = ctrl[1];
     }
   }
+  return HJG_OK;
+}
+
+// ===================================================================== tuning
+namespace {
+// Scratch of the tuning runs, released on every return path.
+struct TuneScratch {
+  void* v = nullptr;
+  void* g = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~TuneScratch() {
+    if (v) (void)hipFree(v);
+    if (g) (void)hipFree(g);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+}  // namespace
+
+extern "C" int hjg_autotune_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N,
+                                  const float* c, const float* theta, int32_t* best_blocks, double* best_ms,
+                                  void* hip_stream) {
+  g_err.clear();
+  int rc = check_common(ctx, p, Q, t, N, 0);
+  if (rc) return rc;
+  if (Q < 1 || !x || !c || !best_blocks || !best_ms) return fail(HJG_EINVAL, "NULL argument or Q < 1");
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  TuneScratch sc;
+  if (hipMalloc(&sc.v, Q * sizeof(float)) != hipSuccess || hipMalloc(&sc.g, (size_t)Q * p->n * sizeof(float)) != hipSuccess)
+    return fail(HJG_ENOMEM, "autotuner scratch allocation failed");
+  float* v = (float*)sc.v;
+  float* g = (float*)sc.g;
+  HJG_HIP(hipEventCreate(&sc.e0));
+  HJG_HIP(hipEventCreate(&sc.e1));
+  hipEvent_t e0 = sc.e0, e1 = sc.e1;
+  const std::string key = sweep_key(p, Q, N);
+  const int candidates[] = {512, 1024, 2048, 4096, 8192, 16384};
+  double best = 1e300;
+  int choice = 2048;
+  for (int cand : candidates) {
+    ctx->tuning[key] = cand;
+    float total = 0.f;
+    for (int rep = 0; rep < 4 && rc == HJG_OK; ++rep) {
+      if (rep == 1) HJG_HIP(hipEventRecord(e0, s));
+      rc = hjg_value_grad(ctx, p, Q, x, t, N, 0, 0, c, theta, v, g, nullptr, 0, hip_stream);
+    }
+    if (rc) break;
+    HJG_HIP(hipEventRecord(e1, s));
+    HJG_HIP(hipEventSynchronize(e1));
+    HJG_HIP(hipEventElapsedTime(&total, e0, e1));
+    if (total / 3.0 < best) {
+      best = total / 3.0;
+      choice = cand;
+    }
+  }
+  if (rc) {
+    ctx->tuning.erase(key);
+    return rc;
+  }
+  ctx->tuning[key] = choice;
+  *best_blocks = choice;
+  *best_ms = best;
+  return HJG_OK;
+}
+
+extern "C" int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* probs, const int64_t* q_off,
+                                    const int32_t* Ns, const int32_t* Ks, const double* ts, double tol,
+                                    const float* x_all, float* v_all, float* grad_all, int32_t* best_split,
+                                    double* best_ms, void* hip_stream) {
+  g_err.clear();
+  if (!ctx || !best_split || !best_ms) return fail(HJG_EINVAL, "NULL argument");
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  TuneScratch sc;
+  HJG_HIP(hipEventCreate(&sc.e0));
+  HJG_HIP(hipEventCreate(&sc.e1));
+  hipEvent_t e0 = sc.e0, e1 = sc.e1;
+  const int candidates[] = {4096, 8192, 16384, 32768, 65536};
+  double best = 1e300;
+  int choice = 16384, rc = HJG_OK;
+  for (int cand : candidates) {
+    ctx->tuning["batch"] = cand;
+    // first call records the plan, the second is timed
+    rc = hjg_picard_sweep_batched(ctx, P, probs, q_off, Ns, Ks, ts, tol, x_all, v_all, grad_all, nullptr, nullptr,
+                                  hip_stream);
+    if (rc) break;
+    HJG_HIP(hipEventRecord(e0, s));
+    rc = hjg_picard_sweep_batched(ctx, P, probs, q_off, Ns, Ks, ts, tol, x_all, v_all, grad_all, nullptr, nullptr,
+                                  hip_stream);
+    if (rc) break;
+    HJG_HIP(hipEventRecord(e1, s));
+    HJG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HJG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      choice = cand;
+    }
+  }
+  if (rc) {
+    ctx->tuning.erase("batch");
+    return rc;
+  }
+  ctx->tuning["batch"] = choice;
+  *best_split = choice;
+  *best_ms = best;
+  return HJG_OK;
+}
+
+extern "C" int hjg_tuning_save(const hjg_ctx* ctx, const char* path) {
+  g_err.clear();
+  if (!ctx || !path) return fail(HJG_EINVAL, "NULL argument");
+  std::ofstream f(path);
+  if (!f) return fail(HJG_EINVAL, std::string("cannot write ") + path);
+  f << "hjg-tuning gfx950 1\n";
+  for (const auto& kv : ctx->tuning) f << kv.first << " = " << kv.second << "\n";
+  return f ? HJG_OK : fail(HJG_EINVAL, std::string("write failed: ") + path);
+}
+
+extern "C" int hjg_tuning_load(hjg_ctx* ctx, const char* path) {
+  g_err.clear();
+  if (!ctx || !path) return fail(HJG_EINVAL, "NULL argument");
+  std::ifstream f(path);
+  if (!f) return fail(HJG_EINVAL, std::string("cannot read ") + path);
+  std::string line;
+  if (!std::getline(f, line) || line.rfind("hjg-tuning gfx950", 0) != 0)
+    return fail(HJG_EINVAL, "not a gfx950 tuning file");
+  std::map<std::string, int> table;
+  while (std::getline(f, line)) {
+    const size_t eq = line.rfind(" = ");
+    if (line.empty()) continue;
+    if (eq == std::string::npos) return fail(HJG_EINVAL, "malformed tuning line: " + line);
+    const int v = std::atoi(line.c_str() + eq + 3);
+    if (v < 1) return fail(HJG_EINVAL, "malformed tuning value: " + line);
+    table[line.substr(0, eq)] = v;
+  }
+  ctx->tuning = table;
   return HJG_OK;
 }
