@@ -26,4 +26,7 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    quasi-linearisation defect is not computable)
   model.hamiltonian (Dubins)     : brute-force max-min over control grids
   model.coefficient              : direct evaluation checks (sign, clip, eta)
+  knn.knn                        : a k-d tree (scipy) on random points, the
+                                   unit-lattice closed form, duplicate points
+                                   and float32 near-ties
 """
