@@ -232,6 +232,35 @@ int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problem
                              int32_t* iters, void* hip_stream);
 
 /*
+ * ------------------------------------------------------------------------
+ * Flock support: k nearest other agents of every agent through a uniform
+ * hash grid (topological neighbour rule of the flocking example).  Their
+ * positions, written as [k][3][M], are the datum_aux of HJG_L_KNN_BALLS with
+ * Q = M (each agent's target set is the union of balls about its
+ * neighbours; union of signed distances is their minimum).
+ *
+ * pos      device float32 [3][M] agent positions (SoA), all finite.
+ * box_lo/hi host float[3]: the grid covers [lo, lo + g h) per axis with
+ *          g = max(1, ceil((hi - lo) / cell)) cells; agents outside are
+ *          clamped into the border cells (results stay exact).
+ * cell     cell edge h > 0; at most 2^20 cells per axis and fewer than 2^26
+ *          in all.
+ * k        neighbours, 1..8; M > k.
+ * idx      device int32 [k][M] or NULL: neighbour indices ordered by
+ *          (squared distance, index), squared distance computed in float32
+ *          as (dx*dx + dy*dy) + dz*dz, each operation rounded; never the
+ *          agent itself.
+ * nbr_pos  device float32 [k][3][M] or NULL: positions of those neighbours.
+ * Exact for any point distribution: shells of cells are searched until no
+ * unsearched cell can hold a nearer agent.  Synchronises the stream once
+ * (the finiteness check of pos) before launching the build and search.
+ * Returns HJG_ENONFINITE for a non-finite position, HJG_EINVAL for bad sizes.
+ */
+int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const float* box_lo,
+                 const float* box_hi, float cell, int32_t k, int32_t* idx, float* nbr_pos,
+                 void* hip_stream);
+
+/*
  * Autotuner.  The pair loop cuts each state's N draws into sample splits so a
  * launch has enough blocks; the split granularity is tuned per kernel
  * specialisation and size bucket (log2 Q, log2 N).

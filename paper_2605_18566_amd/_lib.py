@@ -81,6 +81,8 @@ SIGNATURES = [
                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                            C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                            C.POINTER(C.c_int32), C.c_void_p]),
+    ("hjg_knn_grid", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                               C.c_float, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hjg_autotune_sweep", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double,
                                      C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.c_void_p]),

@@ -263,6 +263,26 @@ def picard_sweep_batched(ctx: Context, specs, xs, N, K, t, tol: float = 0.0, hos
     return out
 
 
+def knn_grid(ctx: Context, pos: torch.Tensor, box_lo, box_hi, cell: float, k: int = 7, want_idx: bool = True,
+             stream=None):
+    """k nearest other agents of each agent via the hash grid.
+
+    pos: device float32 [3, M].  Returns (idx [k, M] int32 or None,
+    nbr [k, 3, M] float32) -- nbr is the datum_aux of the knn_balls datum.
+    """
+    _require_cuda(pos, "pos")
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError("pos must have shape [3, M]")
+    M = pos.shape[1]
+    idx = torch.empty((k, M), dtype=torch.int32, device=pos.device) if want_idx else None
+    nbr = torch.empty((k, 3, M), dtype=torch.float32, device=pos.device)
+    lo = (C.c_float * 3)(*[float(v) for v in box_lo])
+    hi = (C.c_float * 3)(*[float(v) for v in box_hi])
+    check(_lib.lib().hjg_knn_grid(ctx.handle, M, _ptr(pos), lo, hi, float(cell), int(k), _ptr(idx), _ptr(nbr),
+                                  _stream(stream)))
+    return idx, nbr
+
+
 def autotune_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, c: torch.Tensor,
                    theta: Optional[torch.Tensor] = None, stream=None):
     """Tune the sample-split target of this sweep's bucket; returns (blocks, ms)."""

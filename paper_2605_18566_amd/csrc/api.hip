@@ -47,6 +47,7 @@ struct hjg_ctx {
   hipStream_t cap = nullptr;   // stream used only to record graphs
   // workspace
   DevBuf pm, pS, pS2, pG, pZ, vprev, cwork, thwork, blockpart, resid, ctrl, table, zbar;
+  DevBuf g_cell, g_rank, g_start, g_bsum, g_sorted;   // hash grid of the flock search
   // common-table cache
   bool table_valid = false;
   uint64_t t_seed = 0;
@@ -361,7 +362,8 @@ void hjg_ctx_destroy(hjg_ctx* ctx) {
   drop_graphs(ctx);
   for (DevBuf* b : {&ctx->pm, &ctx->pS, &ctx->pS2, &ctx->pG, &ctx->pZ, &ctx->vprev, &ctx->cwork, &ctx->thwork,
                     &ctx->blockpart, &ctx->resid, &ctx->ctrl, &ctx->table, &ctx->zbar, &ctx->batch.ws,
-                    &ctx->batch.args, &ctx->batch.items})
+                    &ctx->batch.args, &ctx->batch.items, &ctx->g_cell, &ctx->g_rank, &ctx->g_start, &ctx->g_bsum,
+                    &ctx->g_sorted})
     if (b->p) (void)hipFree(b->p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -1117,6 +1119,53 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       if (iters) iters[p] = ctrl[1];
     }
   }
+  return HJG_OK;
+}
+
+// ===================================================================== flock
+extern "C" int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const float* box_lo, const float* box_hi,
+                            float cell, int32_t k, int32_t* idx, float* nbr_pos, void* hip_stream) {
+  g_err.clear();
+  if (!ctx) return fail(HJG_EINVAL, "NULL context");
+  if (!pos || !box_lo || !box_hi) return fail(HJG_EINVAL, "pos, box_lo and box_hi are required");
+  if (k < 1 || k > kMaxKnn) return fail(HJG_EINVAL, "k must be in 1..8");
+  if (M < k + 1) return fail(HJG_EINVAL, "need more than k agents");
+  if (M > INT32_MAX) return fail(HJG_EINVAL, "at most 2^31 - 1 agents");
+  if (!(std::isfinite(cell) && cell > 0.f)) return fail(HJG_EINVAL, "cell must be finite and > 0");
+  GridGeom gg{};
+  int64_t cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (!(std::isfinite(box_lo[d]) && std::isfinite(box_hi[d]) && box_hi[d] >= box_lo[d]))
+      return fail(HJG_EINVAL, "box must be finite with hi >= lo");
+    const double gd = std::ceil(((double)box_hi[d] - box_lo[d]) / cell);
+    if (gd > (double)(1 << 20)) return fail(HJG_EINVAL, "more than 2^20 cells along one axis");
+    gg.g[d] = std::max(1, (int)gd);
+    gg.lo[d] = box_lo[d];
+    cells *= gg.g[d];
+  }
+  if (cells >= kMaxGridCells) return fail(HJG_EINVAL, "2^26 or more grid cells; use a larger cell");
+  gg.h = cell;
+  gg.inv_h = 1.f / cell;
+  if (!idx && !nbr_pos) return HJG_OK;
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  int rc;
+  const int64_t nb = (cells + 1 + 4095) / 4096;
+  if ((rc = ensure(ctx, ctx->g_cell, M * sizeof(int))) || (rc = ensure(ctx, ctx->g_rank, M * sizeof(int))) ||
+      (rc = ensure(ctx, ctx->g_start, (cells + 1) * sizeof(int))) || (rc = ensure(ctx, ctx->g_bsum, nb * sizeof(int))) ||
+      (rc = ensure(ctx, ctx->g_sorted, M * sizeof(float4))) || (rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int))))
+    return rc;
+  // positions must be finite: the cell of a NaN is not defined
+  int* flag = (int*)ctx->ctrl.p + 3;
+  HJG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  HJG_HIP(launch_finite_check(pos, 3 * M, flag, s));
+  int host = 0;
+  HJG_HIP(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HJG_HIP(hipStreamSynchronize(s));
+  if (host) return fail(HJG_ENONFINITE, "non-finite agent position");
+  HJG_HIP(launch_grid_build(pos, M, gg, (int*)ctx->g_cell.p, (int*)ctx->g_rank.p, (int*)ctx->g_start.p,
+                            (int*)ctx->g_bsum.p, (float4*)ctx->g_sorted.p, s));
+  HJG_HIP(launch_knn((const float4*)ctx->g_sorted.p, (const int*)ctx->g_start.p, M, gg, k, idx, nbr_pos, s));
   return HJG_OK;
 }
 

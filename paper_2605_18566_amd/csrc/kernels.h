@@ -136,6 +136,24 @@ hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c
                                uint32_t* out, hipStream_t s);
 hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
 
+// Uniform hash grid over agent positions: cell (x, y, z) covers
+// [lo + (x, y, z) h, lo + (x+1, y+1, z+1) h); positions outside are clamped
+// into the border cells.
+struct GridGeom {
+  float lo[3];
+  float h, inv_h;
+  int g[3];
+};
+constexpr int64_t kMaxGridCells = int64_t(1) << 26;
+// pos [3][M]; cell, rank [M]; start [cells + 1] (becomes the exclusive scan
+// of the per-cell counts); bsum [ceil((cells + 1) / 4096)]; sorted [M]
+// (x, y, z, agent index bits) in cell order.
+hipError_t launch_grid_build(const float* pos, int64_t M, const GridGeom& gg, int* cell, int* rank, int* start,
+                             int* bsum, float4* sorted, hipStream_t s);
+// k (1..8) nearest other agents: idx [k][M], nbr [k][3][M] (either may be null).
+hipError_t launch_knn(const float4* sorted, const int* start, int64_t M, const GridGeom& gg, int k, int32_t* idx,
+                      float* nbr, hipStream_t s);
+
 // Queries per block of the two pair-loop kernels.
 constexpr int kQueriesPerBlockValu = 256;
 constexpr int kQueriesPerBlockMfma = 128;

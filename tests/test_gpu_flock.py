@@ -1,0 +1,166 @@
+"""Flock support on an MI355X: the hash-grid k-nearest-neighbour search against
+the brute-force oracle (identical index sets and orders), its edge cases, and
+the per-agent Picard sweep on the flock target sets against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import estimator
+from oracle import knn as oknn
+from tests._helpers import gpu_problem, oracle_problem, to_dev, value_tol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2605_18566_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def gpu_knn(ctx, pos, k=7, lo=None, hi=None, cell=workloads.FLOCK_CELL):
+    from paper_2605_18566_amd import knn_grid
+    pos = np.asarray(pos, np.float32)
+    lo = pos.min(0) if lo is None else lo
+    hi = pos.max(0) if hi is None else hi
+    print(f"[knn] M={len(pos)} k={k} cell={cell} lo={np.round(lo, 3)} hi={np.round(hi, 3)}", flush=True)
+    idx, nbr = knn_grid(ctx, to_dev(np.ascontiguousarray(pos.T)), lo, hi, cell, k)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy().T, nbr.cpu().numpy()         # [M, k], [k, 3, M]
+
+
+def check_against_oracle(pos, idx, nbr, queries=None):
+    qs = np.arange(len(pos)) if queries is None else np.asarray(queries)
+    ref = oknn.knn(pos, idx.shape[1], queries=qs)
+    np.testing.assert_array_equal(idx[qs], ref)
+    k = idx.shape[1]
+    np.testing.assert_array_equal(nbr[:, :, qs], np.transpose(pos[ref], (1, 2, 0)).reshape(k, 3, len(qs)))
+
+
+def test_knn_matches_brute_force_at_flock_density(ctx):
+    pos = workloads.flock_agents(6000, trial=1)[:, :3]
+    idx, nbr = gpu_knn(ctx, pos, lo=(0, 0, 0), hi=(50 * 0.06 ** (1 / 3),) * 3)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_full_flock_sampled(ctx):
+    pos = workloads.flock_agents(workloads.C4.Q, trial=0)[:, :3]
+    idx, nbr = gpu_knn(ctx, pos, lo=(0, 0, 0), hi=(50, 50, 50))
+    sample = np.random.default_rng(5).choice(len(pos), 300, replace=False)
+    check_against_oracle(pos, idx, nbr, sample)
+    # the index sets hold distinct agents and never the agent itself
+    assert np.all(idx != np.arange(len(pos))[:, None])
+    s = np.sort(idx, 1)
+    assert np.all(s[:, 1:] != s[:, :-1])
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_knn_each_k(ctx, k):
+    pos = workloads.flock_agents(3000, trial=2)[:, :3]
+    idx, nbr = gpu_knn(ctx, pos, k=k, cell=1.5)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_duplicates_break_ties_by_index(ctx):
+    rng = np.random.default_rng(3)
+    base = rng.uniform(0, 6, (200, 3)).astype(np.float32)
+    pos = np.concatenate([base, base, base[:50]])            # every point two or three times
+    idx, nbr = gpu_knn(ctx, pos, cell=1.0)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_sparse_points_need_wide_shells(ctx):
+    # 20 agents in a 100^3 box with cell 1: neighbours lie many cells away
+    pos = np.random.default_rng(4).uniform(0, 100, (20, 3)).astype(np.float32)
+    idx, nbr = gpu_knn(ctx, pos, k=7, lo=(0, 0, 0), hi=(100, 100, 100), cell=4.0)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_clustered_and_outside_the_box(ctx):
+    rng = np.random.default_rng(6)
+    cluster = rng.normal(0, 0.05, (500, 3))
+    far = rng.uniform(-30, 30, (300, 3))                     # most of these lie outside the box
+    pos = np.concatenate([cluster, far]).astype(np.float32)
+    idx, nbr = gpu_knn(ctx, pos, lo=(-1, -1, -1), hi=(1, 1, 1), cell=0.5)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_minimum_agents_and_one_cell(ctx):
+    pos = np.random.default_rng(7).uniform(0, 1, (8, 3)).astype(np.float32)
+    idx, nbr = gpu_knn(ctx, pos, k=7, cell=10.0)
+    check_against_oracle(pos, idx, nbr)
+
+
+def test_knn_rejects_bad_input(ctx):
+    from paper_2605_18566_amd import knn_grid
+    from paper_2605_18566_amd._lib import HJG_EINVAL, HJG_ENONFINITE, HJGError
+    pos = to_dev(np.random.default_rng(8).uniform(0, 1, (3, 7)))
+    with pytest.raises(HJGError) as e:
+        knn_grid(ctx, pos, (0, 0, 0), (1, 1, 1), 0.5, 7)                 # M = 7 = k
+    assert e.value.code == HJG_EINVAL
+    with pytest.raises(HJGError) as e:
+        knn_grid(ctx, pos, (0, 0, 0), (1e4, 1e4, 1e4), 0.01, 3)          # 10^18 cells
+    assert e.value.code == HJG_EINVAL
+    bad = pos.clone()
+    bad[1, 3] = float("nan")
+    with pytest.raises(HJGError) as e:
+        knn_grid(ctx, bad, (0, 0, 0), (1, 1, 1), 0.5, 3)
+    assert e.value.code == HJG_ENONFINITE
+
+
+def _flock_sweep(ctx, M, N, K, t, step, trial):
+    """GPU: grid search + Picard sweep over all agents.  Returns what the oracle needs."""
+    from paper_2605_18566_amd import knn_grid, picard_sweep
+    w = workloads.C4
+    st = workloads.flock_agents(M, trial=trial)
+    pos_d = to_dev(np.ascontiguousarray(st[:, :3].T))
+    ext = workloads.FLOCK_EXTENT * (M / 100000) ** (1 / 3)
+    idx, nbr = knn_grid(ctx, pos_d, (0, 0, 0), (ext,) * 3, workloads.FLOCK_CELL, 7)
+    fields = w.problem_fields()
+    out = picard_sweep(ctx, gpu_problem(fields, aux=nbr), to_dev(np.ascontiguousarray(st.T)), t, N, K,
+                       time_step=step)
+    torch.cuda.synchronize()
+    return st, idx.cpu().numpy().T, out, fields
+
+
+@pytest.mark.parametrize("t,step", [(0.2, 1), (1.0, 5)])
+def test_flock_picard_matches_oracle(ctx, t, step):
+    M, N, K = 2500, 1024, 3
+    st, idx, out, fields = _flock_sweep(ctx, M, N, K, t, step, trial=3)
+    ref_idx = oknn.knn(st[:, :3], 7)
+    np.testing.assert_array_equal(idx, ref_idx)
+    nb = st[:, :3][ref_idx].astype(np.float64)                   # [M, 7, 3]
+    pb = oracle_problem(fields, aux=nb)
+    x = st.astype(np.float64)
+    ref = estimator.picard(pb, x, t, N, K, time_step=step)
+    sigma = np.sqrt(pb.delta * t)
+    v = out.v.cpu().numpy()
+    vt = 10 * value_tol(ref.v, ref.c, ref.theta, sigma, ref.lmax)
+    frac = np.mean(np.abs(v - ref.v) <= vt)
+    print(f"[flock picard t={t}] within tol {frac:.4f}, max |dv| {np.abs(v - ref.v).max():.2e}", flush=True)
+    assert frac >= 0.995
+    np.testing.assert_allclose(out.resid_hist, ref.resid_hist, rtol=2e-2, atol=1e-6)
+
+
+def test_flock_full_size_sampled_agents(ctx):
+    # the full 100,000-agent flock in the launch shape the benchmark times;
+    # queries do not interact (tol = 0), so sampled agents can be recomputed
+    # one by one by the oracle with their neighbours
+    w = workloads.C4
+    st, idx, out, fields = _flock_sweep(ctx, w.Q, w.N, w.K, 0.6, 3, trial=0)
+    sample = np.random.default_rng(9).choice(w.Q, 48, replace=False)
+    ref_idx = oknn.knn(st[:, :3], 7, queries=sample)
+    np.testing.assert_array_equal(idx[sample], ref_idx)
+    nb = st[:, :3][ref_idx].astype(np.float64)
+    pb = oracle_problem(fields, aux=nb)
+    ref = estimator.picard(pb, st[sample].astype(np.float64), 0.6, w.N, w.K, time_step=3)
+    sigma = np.sqrt(pb.delta * 0.6)
+    v = out.v.cpu().numpy()[sample]
+    vt = 10 * value_tol(ref.v, ref.c, ref.theta, sigma, ref.lmax)
+    frac = np.mean(np.abs(v - ref.v) <= vt)
+    print(f"[flock full] within tol {frac:.4f}, max |dv| {np.abs(v - ref.v).max():.2e}", flush=True)
+    assert frac >= 47 / 48

@@ -106,6 +106,28 @@ C5 = Workload("c5_dubins15_n45", n=45, ham="dubins_pairs", datum="min_pair_disks
 C5Q = replace(C5, name="c5q_quadratic15_n45", ham="quadratic", tube=False, cfg=6)
 
 
+# Flock safety: 100,000 agents with 6D states (position uniform in [0, 50]^3,
+# velocity N(0, 0.5^2 I)); an agent's target set is the union of balls of
+# radius 0.2 about its 7 nearest other agents (hash grid with cell 2);
+# double-integrator H with |u| <= 1, tube coefficient, nu = 0.02, T = 1 in 5
+# horizons, 3 iterations, N = 4,096 bfloat16 common draws, Laplace shift.
+C4 = Workload("c4_flock_n6", n=6, ham="double_integrator", ham_p=(1.0,), datum="knn_balls", datum_p=(0.2, 7),
+              nu=0.02, t=1.0, Q=100000, N=4096, K=3, box=((0.0, 50.0),) * 3 + ((-1.5, 1.5),) * 3, tilt=True,
+              sample_mode="crn_step", sample_bf16=True, cfg=4, time_steps=5, T=1.0, tube=True)
+FLOCK_EXTENT, FLOCK_CELL, FLOCK_VEL_STD = 50.0, 2.0, 0.5
+
+
+def flock_agents(M: int = 100000, trial: int = 0, extent: Optional[float] = None) -> np.ndarray:
+    """Agent states [M, 6] float32: positions uniform in [0, extent]^3 (default:
+    the 100,000-agent density, extent 50 (M / 1e5)^(1/3)), velocities N(0, 0.5^2 I)."""
+    if extent is None:
+        extent = FLOCK_EXTENT * (M / 100000) ** (1.0 / 3.0)
+    g = rng(4, trial)
+    pos = g.uniform(0.0, extent, (M, 3))
+    vel = g.normal(0.0, FLOCK_VEL_STD, (M, 3))
+    return np.concatenate([pos, vel], 1).astype(np.float32)
+
+
 def horizons(w: Workload):
     """Time-to-go of each horizon: t_j = j T / S_t, j = 1..S_t."""
     return [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
