@@ -11,8 +11,9 @@ Prints one JSON line with the throughput, the roofline of the dominant kernel
 (the pair loop, timed by HIP events around every launch inside the timed
 region), the FP64 CPU oracle timed on a bounded sample of the same workload,
 the estimator's health on that workload (ESS, Picard residuals), the
-surrogate-vs-plain study at equal RMS value error and the uneven-batch study
-(one batched graph vs one call per problem).
+surrogate-vs-plain study at equal RMS value error, the uneven-batch study
+(one batched graph vs one call per problem) and the flock study (hash-grid
+7-NN search and the per-agent sweep over 100,000 agents).
 """
 from __future__ import annotations
 
@@ -27,28 +28,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "query·samples/s for v,∇v at n=45; surrogate vs plain MC at equal RMS error"
 
-# Chip figures used for the roofline (MI355X, gfx950).
-CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
-VALU_PEAK = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ     # 3.93e13 VALU lane-op slots / s
+# Chip figures used for the roofline (MI355X, gfx950).  The FP32 vector peak,
+# 157.3 TFLOP/s, is 2 flops per FMA on 256 CUs x 128 lanes x 2.4 GHz: 7.86e13
+# full-rate lane operations per second (FMA, MUL, ADD, logic).  Measured on
+# this chip: min/max/min3, DPP operands and conversions issue at half that
+# rate and transcendentals (sqrt, exp2) at a quarter.
+CUS, LANE_SLOTS_PER_CLK, CLOCK_HZ = 256, 128, 2.4e9
+VALU_PEAK = CUS * LANE_SLOTS_PER_CLK * CLOCK_HZ     # 7.86e13 full-rate lane-op slots / s
 
 
 def alu_slots_per_pair(datum: str, n: int) -> int:
-    """Minimum VALU lane-op slots per (query, sample) pair that are not a dense contraction.
+    """Minimum full-rate VALU lane-op slots per (query, sample) pair outside the
+    dense contractions, for the stacked-disc datum with m = n/3 pairs.
 
-    min_pair_disks with m = n/3 pairs: per pair 2 FMA (y), MUL + FMA (|y|^2),
-    MIN -> 5m - 1; sqrt (transcendental, 2 slots) and the radius subtraction
-    -> 3; the log-weight a = -c l + (a0 - <z, theta>) -> 2; running max -> 1;
-    exp2(a - m) (sub + 2 slots) -> 3; S += w, S2 += w^2 -> 2.  Total 5m + 10.
-    The two contractions <z, theta> and sum w z (2n MACs) belong to MFMA and
-    are not counted.
+    y = x + theta + sigma z on the 2m planar coordinates -> 2m FMA; |y_k|^2 ->
+    m (MUL + FMA); the minimum over m values -> m - 1 compares (two per min3,
+    which issues at half rate: one slot per compare); sqrt (4 slots) and the
+    radius -> 5; the log-weight a = -c l + (a0 - <z, theta>) -> 2; running
+    maximum -> 1; exp2(a - m) -> 1 + 4; S += w, S2 += w^2 -> 2.  Total
+    5m + 14.  The two contractions <z, theta> and sum w z (2n MACs) run on the
+    matrix cores and are not counted.
     """
     if datum == "min_pair_disks":
-        return 5 * (n // 3) + 10
+        return 5 * (n // 3) + 14
     raise ValueError(datum)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "pair_loop_dubins15_n45_mfma.md")
-KERNEL_SOURCES = ["sweep_mfma.h", "sweep_impl.h", "kernels.h", "device.h"]
+def alu_slots_knn_pair(k: int, n: int) -> int:
+    """Minimum full-rate VALU lane-op slots per pair for the flock datum (k
+    neighbour balls).
+
+    y on the 3 position coordinates -> 3 FMA; per neighbour 3 SUB, MUL + 2 FMA
+    -> 6k, the minimum over k -> k - 1 compares; sqrt (4 slots) and the radius
+    -> 5; a -> 2; running maximum -> 1; exp2 -> 5; S, S2 -> 2.  At n = 6 the
+    pair loop runs on the vector ALUs, so the two contractions <z, theta> and
+    sum w z (2n FMA) count too: 7k + 17 + 2n.
+    """
+    return 7 * k + 17 + 2 * n
+
+
+PROFILE = os.path.join(ROOT, "profiles", "pair_loop_dubins15_n45.md")
+KERNEL_SOURCES = ["sweep_pairs.h", "sweep_mfma.h", "sweep_impl.h", "kernels.h", "device.h"]
 
 
 def measured_traffic():
@@ -225,6 +245,73 @@ def batched_study(ctx, stream, P: int = 256):
             "one_call_per_problem_includes": "per-call table generation and graph recording (16-graph cache)"}
 
 
+def flock_study(ctx, stream):
+    """The 100,000-agent flock: hash-grid 7-NN search, then the Picard sweep
+    (K = 3, N = 4,096 bf16 common draws) at the 5 horizons t_j = 0.2 j."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, knn_grid, picard_sweep
+    w = workloads.C4
+    dev = torch.device("cuda:0")
+    st = workloads.flock_agents(w.Q, trial=0)
+    pos = torch.from_numpy(np.ascontiguousarray(st[:, :3].T)).to(dev)
+    x = torch.from_numpy(np.ascontiguousarray(st.T)).to(dev)
+    ext = workloads.FLOCK_EXTENT
+    k = int(w.datum_p[1])
+    with torch.cuda.stream(stream):
+        _, nbr = knn_grid(ctx, pos, (0, 0, 0), (ext,) * 3, workloads.FLOCK_CELL, k, want_idx=False, stream=stream)
+        reps = 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            knn_grid(ctx, pos, (0, 0, 0), (ext,) * 3, workloads.FLOCK_CELL, k, want_idx=False, stream=stream)
+        torch.cuda.synchronize()
+        knn_ms = (time.perf_counter() - t0) / reps * 1e3
+        spec = ProblemSpec(datum_aux=nbr, **w.problem_fields())
+        hs = workloads.horizons(w)
+
+        def sweep_all(out=None):
+            outs = []
+            for j, t in enumerate(hs):
+                outs.append(picard_sweep(ctx, spec, x, t, w.N, w.K, time_step=j + 1, host_outputs=False,
+                                         stream=stream))
+            return outs
+        sweep_all()                                        # records one graph per horizon
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = sweep_all()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.set_timing(True)
+        kernel_ms, launches = 0.0, 0
+        for j, t in enumerate(hs):
+            picard_sweep(ctx, spec, x, t, w.N, w.K, time_step=j + 1, host_outputs=False, stream=stream)
+            ms, nl = ctx.sweep_time()
+            kernel_ms += ms
+            launches += nl
+        ctx.set_timing(False)
+        last = picard_sweep(ctx, spec, x, hs[-1], w.N, w.K, time_step=len(hs), stream=stream)
+    v = torch.stack([o.v for o in outs]).cpu().numpy()
+    if not np.all(np.isfinite(v)):
+        raise RuntimeError("non-finite values in the flock study")
+    pairs = float(w.Q * w.N * w.K * len(hs))
+    slots = alu_slots_knn_pair(k, w.n)
+    per_launch = kernel_ms / max(launches, 1)
+    achieved = slots * w.Q * w.N / (per_launch * 1e-3)
+    return {"workload": f"{w.name}: {w.Q} agents, 7-NN union-of-balls target (r = 0.2), double integrator, "
+                        f"nu = {w.nu}, {len(hs)} horizons x K = {w.K}, N = {w.N} bf16 common draws, tube coefficient",
+            "knn_grid_ms": knn_ms,
+            "sweep_seconds_all_horizons": dt,
+            "query_samples_per_s": pairs / dt,
+            "pair_loop": {"bound": "alu", "alu_slots_per_pair": slots, "kernel_ms_per_launch": per_launch,
+                          "achieved_TOPs": achieved / 1e12, "frac": achieved / VALU_PEAK},
+            "health_last_horizon": {"resid_hist": [float(r) for r in last.resid_hist],
+                                    "ess_median": float(np.median(last.ess.cpu().numpy())),
+                                    "frac_v_below_zero": float(np.mean(last.v.cpu().numpy() < 0))}}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -260,6 +347,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the equal-accuracy surrogate study")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch study")
+    ap.add_argument("--no-flock", action="store_true", help="skip the flock study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -335,6 +423,9 @@ def main():
     bstudy = None
     if not args.no_batched:
         bstudy = batched_study(ctx, stream)
+    fstudy = None
+    if not args.no_flock:
+        fstudy = flock_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -363,12 +454,13 @@ def main():
                    "datum": w.datum},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
-                     "kernel": "pair loop (sweep_mfma_kernel<min_pair_disks, 48, 15>)", "kernel_ms_per_launch": per_launch_ms,
+                     "kernel": "pair loop (sweep_pairs_kernel<48, 15>)", "kernel_ms_per_launch": per_launch_ms,
                      "launches_timed": launches, "alu_slots_per_pair": slots},
         "cpu_baseline": cpu,
         "estimator_health": health,
         "surrogate": study,
         "batched": bstudy,
+        "flock": fstudy,
     }
     print(json.dumps(line))
 

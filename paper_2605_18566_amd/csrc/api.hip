@@ -54,6 +54,8 @@ struct hjg_ctx {
   uint32_t t_pid = 0, t_step = 0;
   int t_n = 0, t_N = 0, t_bf16 = 0;
   int64_t t_stride = 0;
+  int t_zd = 0;          // the table buffer also holds the pair-coordinate copy
+  int64_t t_zoff = 0;    // its byte offset
   int zbar_valid = 0;
   // recorded Picard graphs
   struct Graph {
@@ -226,6 +228,15 @@ bool use_mfma(const hjg_problem* p) {
   return p->sample_mode == HJG_S_CRN_STEP && p->sample_bf16 && p->n >= 16 && p->datum != HJG_L_KNN_BALLS;
 }
 
+// Stacked disc pairs on the matrix cores use the one-query-per-lane kernel,
+// which reads a float32 sample-major copy of the pair coordinates.
+bool pairs_kernel(const hjg_problem* p) { return use_mfma(p) && p->datum == HJG_L_MIN_PAIR_DISKS; }
+
+int queries_per_block(const hjg_problem* p) {
+  if (pairs_kernel(p)) return kQueriesPerBlockPairs;
+  return use_mfma(p) ? kQueriesPerBlockMfma : kQueriesPerBlockValu;
+}
+
 struct Plan {
   int splits;
   int ns;
@@ -280,13 +291,21 @@ Partials partials(hjg_ctx* ctx) {
 int ensure_table(hjg_ctx* ctx, const hjg_problem* p, int N, uint32_t step, bool need_zbar, hipStream_t s) {
   const bool bf16 = p->sample_bf16 != 0;
   const int64_t tstride = div_up(N, 64) * 64;
+  const bool zd = pairs_kernel(p);
   const bool hit = ctx->table_valid && ctx->t_seed == p->seed && ctx->t_pid == p->problem_id &&
-                   ctx->t_step == step && ctx->t_n == p->n && ctx->t_N == N && ctx->t_bf16 == (int)bf16;
+                   ctx->t_step == step && ctx->t_n == p->n && ctx->t_N == N && ctx->t_bf16 == (int)bf16 &&
+                   (!zd || ctx->t_zd);
   int rc;
   if (!hit) {
-    if ((rc = ensure(ctx, ctx->table, (size_t)p->n * tstride * (bf16 ? 2 : 4)))) return rc;
+    const int64_t tbytes = (int64_t)p->n * tstride * (bf16 ? 2 : 4);
+    const int64_t zoff = (tbytes + 255) / 256 * 256;
+    const int zs = pair_coord_stride(p->n / 3);
+    if ((rc = ensure(ctx, ctx->table, zd ? (size_t)(zoff + (int64_t)N * zs * 4) : (size_t)tbytes))) return rc;
     const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
     HJG_HIP(launch_table(p->n, tstride, tstride, k0, k1, make_tag(p->problem_id, step, 0), bf16, ctx->table.p, s));
+    if (zd) HJG_HIP(launch_pair_coords(p->n / 3, N, tstride, ctx->table.p, zs, (float*)((char*)ctx->table.p + zoff), s));
+    ctx->t_zd = zd;
+    ctx->t_zoff = zoff;
     ctx->table_valid = true;
     ctx->t_seed = p->seed;
     ctx->t_pid = p->problem_id;
@@ -303,6 +322,10 @@ int ensure_table(hjg_ctx* ctx, const hjg_problem* p, int N, uint32_t step, bool 
     ctx->zbar_valid = 1;
   }
   return HJG_OK;
+}
+
+const float* table_zd(const hjg_ctx* ctx, const hjg_problem* p) {
+  return pairs_kernel(p) && ctx->t_zd ? (const float*)((const char*)ctx->table.p + ctx->t_zoff) : nullptr;
 }
 
 int ensure_events(hjg_ctx* ctx) {
@@ -408,8 +431,7 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const bool mf = use_mfma(p);
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
-  const Plan pl = plan_splits(Q, N, fresh, mf ? kQueriesPerBlockMfma : kQueriesPerBlockValu,
-                              tv == ctx->tuning.end() ? 0 : tv->second);
+  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p), tv == ctx->tuning.end() ? 0 : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
   const float sigma = (float)std::sqrt(2.0 * p->nu * t);
@@ -426,6 +448,7 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   a.sigma = sigma;
   a.table = fresh ? nullptr : ctx->table.p;
   a.tstride = ctx->t_stride;
+  a.zd = fresh ? nullptr : table_zd(ctx, p);
   a.dp = datum_params(p);
   a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
   a.k1 = (uint32_t)(p->seed >> 32);
@@ -565,6 +588,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
     a.sigma = sigma;
     a.table = fresh ? nullptr : ctx->table.p;
     a.tstride = ctx->t_stride;
+    a.zd = fresh ? nullptr : table_zd(ctx, p);
     a.dp = in.dp;
     a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(p->seed >> 32);
@@ -640,8 +664,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
-  const Plan pl = plan_splits(Q, N, fresh, use_mfma(p) ? kQueriesPerBlockMfma : kQueriesPerBlockValu,
-                              tv == ctx->tuning.end() ? 0 : tv->second);
+  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p), tv == ctx->tuning.end() ? 0 : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
@@ -843,7 +866,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       int64_t Q, qb_sweep, qb256;
       int splits, ns, mfma, bf16;
       int64_t tstride;
-      int64_t o_m, o_S, o_S2, o_G, o_vp, o_c, o_th, o_bp, o_res, o_ctrl, o_tab, o_zb;
+      int64_t o_m, o_S, o_S2, o_G, o_vp, o_c, o_th, o_bp, o_res, o_ctrl, o_tab, o_zb, o_zd;
     };
     std::vector<Plan1> pl(P);
     int64_t off = 0;
@@ -858,7 +881,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       q.Q = q_off[p + 1] - q_off[p];
       q.mfma = use_mfma(&pr);
       q.bf16 = pr.sample_bf16 != 0;
-      const int qpb = q.mfma ? kQueriesPerBlockMfma : kQueriesPerBlockValu;
+      const int qpb = queries_per_block(&pr);
       q.qb_sweep = div_up(q.Q, qpb);
       q.qb256 = div_up(q.Q, kThreads);
       q.ns = std::min<int64_t>(split_ns, div_up(Ns[p], kBlk) * kBlk);
@@ -877,6 +900,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       q.o_ctrl = take(16);
       q.o_tab = take((int64_t)pr.n * q.tstride * (q.bf16 ? 2 : 4));
       q.o_zb = pr.grad_cv ? take(pr.n * 8) : -1;
+      q.o_zd = pairs_kernel(&pr) ? take((int64_t)Ns[p] * pair_coord_stride(pr.n / 3) * 4) : -1;
     }
     int rc;
     if ((rc = ensure(ctx, B.ws, off))) return rc;
@@ -911,6 +935,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       A.sigma = sigma;
       A.table = at(q.o_tab);
       A.tstride = q.tstride;
+      A.zd = (const float*)at(q.o_zd);
       A.dp = datum_params(&pr);
       A.k0 = (uint32_t)(pr.seed & 0xFFFFFFFFu);
       A.k1 = (uint32_t)(pr.seed >> 32);
@@ -1067,6 +1092,9 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
                            at(pl[p].o_tab), s));
       if (pr.grad_cv)
         HJG_HIP(launch_zbar(pr.n, Ns[p], pl[p].tstride, pl[p].bf16, at(pl[p].o_tab), (double*)at(pl[p].o_zb), s));
+      if (pl[p].o_zd >= 0)
+        HJG_HIP(launch_pair_coords(pr.n / 3, Ns[p], pl[p].tstride, at(pl[p].o_tab), pair_coord_stride(pr.n / 3),
+                                   (float*)at(pl[p].o_zd), s));
     }
     HJG_HIP(hipStreamSynchronize(s));
 

@@ -39,6 +39,8 @@ struct SweepArgs {
   float sigma;
   const void* table;   // [n][tstride] float32 or bf16 bits (CRN)
   int64_t tstride;
+  const float* zd;     // stacked disc pairs on the matrix cores: [N][zs] float32
+                       // copy of each sample's 2m planar coordinates, else nullptr
   DatumP dp;
   uint32_t k0, k1, tag;  // Philox key and tag (FRESH)
   int cv;                // FRESH: also accumulate sum z
@@ -132,6 +134,8 @@ hipError_t launch_reduce_batched(const ReduceArgs* args, const int* plist, int c
 hipError_t launch_table(int n, int64_t limit, int64_t tstride, uint32_t k0, uint32_t k1, uint32_t tag, int bf16,
                         void* out, hipStream_t s);
 hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s);
+// zd[i][2k + e] = table[3k + e][i] (bf16 -> float32, k < m, e < 2), zero up to zs.
+hipError_t launch_pair_coords(int m, int N, int64_t tstride, const void* table_bf16, int zs, float* zd, hipStream_t s);
 hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G,
                                uint32_t* out, hipStream_t s);
 hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
@@ -154,9 +158,13 @@ hipError_t launch_grid_build(const float* pos, int64_t M, const GridGeom& gg, in
 hipError_t launch_knn(const float4* sorted, const int* start, int64_t M, const GridGeom& gg, int k, int32_t* idx,
                       float* nbr, hipStream_t s);
 
-// Queries per block of the two pair-loop kernels.
+// Queries per block of the pair-loop kernels: vector ALU, generic matrix
+// core, stacked disc pairs on the matrix cores (one query per lane).
 constexpr int kQueriesPerBlockValu = 256;
 constexpr int kQueriesPerBlockMfma = 128;
+constexpr int kQueriesPerBlockPairs = 512;
+// Floats per sample in the pair-coordinate copy: 2m rounded up to 8.
+constexpr int pair_coord_stride(int m) { return ((2 * m + 7) / 8) * 8; }
 
 // Smallest register bucket that holds n dimensions.
 inline int n_bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 48; }

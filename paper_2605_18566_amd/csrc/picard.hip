@@ -272,6 +272,22 @@ hipError_t launch_table(int n, int64_t limit, int64_t tstride, uint32_t k0, uint
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kThreads) void pair_coords_kernel(int m, int N, int64_t tstride, const uint16_t* table,
+                                                               int zs, float* zd) {
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= (int64_t)N * zs) return;
+  const int64_t i = idx / zs;
+  const int s = (int)(idx % zs);
+  zd[idx] = s < 2 * m ? bf16_to_f32(table[(int64_t)(3 * (s / 2) + s % 2) * tstride + i]) : 0.f;
+}
+
+hipError_t launch_pair_coords(int m, int N, int64_t tstride, const void* table_bf16, int zs, float* zd, hipStream_t s) {
+  const int64_t work = (int64_t)N * zs;
+  pair_coords_kernel<<<(unsigned)((work + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+      m, N, tstride, static_cast<const uint16_t*>(table_bf16), zs, zd);
+  return hipGetLastError();
+}
+
 hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s) {
   zbar_kernel<<<n, kThreads, 0, s>>>(N, tstride, bf16, table, zbar);
   return hipGetLastError();

@@ -18,6 +18,7 @@
 
 #include "kernels.h"
 #include "sweep_mfma.h"
+#include "sweep_pairs.h"
 
 namespace hjg {
 
@@ -341,7 +342,16 @@ __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
 template <int DATUM, int NM, int MP>
 hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
   if (a.mfma) {
-    if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
+    if constexpr (NM >= 16 && DATUM == HJG_L_MIN_PAIR_DISKS) {
+      if (fresh || !bf16) return hipErrorInvalidValue;
+      if (b) {
+        sweep_pairs_batched_kernel<NM, MP><<<b->count, kPThreads, 0, s>>>(b->probs, b->items);
+      } else {
+        const dim3 grid((unsigned)((a.Q + kPQ - 1) / kPQ), (unsigned)a.splits);
+        sweep_pairs_kernel<NM, MP><<<grid, kPThreads, 0, s>>>(a);
+      }
+      return hipGetLastError();
+    } else if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
       if (fresh || !bf16) return hipErrorInvalidValue;
       if (b) {
         sweep_mfma_batched_kernel<DATUM, NM, MP><<<b->count, 256, 0, s>>>(b->probs, b->items);
