@@ -259,8 +259,13 @@ std::string sweep_key(const hjg_problem* p, int64_t Q, int N) {
   return k.str();
 }
 
-Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block, int tuned = 0) {
-  int target = tuned > 0 ? tuned : 2048;
+// Default number of blocks a sweep launch aims for: the one-query-per-lane
+// kernel holds one 8-wave block per CU, so two rounds of blocks (512) keep
+// every CU busy with the fewest sample splits; the other kernels run 2 to 4
+// smaller blocks per CU.
+int default_target_blocks(const hjg_problem* p) { return pairs_kernel(p) ? 512 : 2048; }
+
+Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block, int target) {
   if (const char* e = std::getenv("HJG_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
   const int64_t qblocks = div_up(Q, queries_per_block);
   const int gran = fresh ? 64 : kBlk;
@@ -431,7 +436,8 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const bool mf = use_mfma(p);
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
-  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p), tv == ctx->tuning.end() ? 0 : tv->second);
+  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p),
+                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
   const float sigma = (float)std::sqrt(2.0 * p->nu * t);
@@ -664,7 +670,8 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   hipStream_t s = (hipStream_t)hip_stream;
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
-  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p), tv == ctx->tuning.end() ? 0 : tv->second);
+  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p),
+                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
