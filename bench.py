@@ -457,6 +457,12 @@ def main():
                      "kernel": "pair loop (sweep_pairs_kernel<48, 15>)", "kernel_ms_per_launch": per_launch_ms,
                      "launches_timed": launches, "alu_slots_per_pair": slots},
         "cpu_baseline": cpu,
+        # the paper reports CPU timings only: ~2.0e7 query.samples.iterations/s
+        # on one core (derived from its 3D Dubins and rocket slice timings)
+        "paper_context": {"value": 2.0e7, "unit": "query·samples/s (K iterations counted)",
+                          "hardware": "1 core of an Intel Core i7-14700K, JAX CPU backend",
+                          "workload": "3D pursuit-evasion slices: 1,600 states, N = 14,000-20,000, K = 12-15",
+                          "note": "context only: different workload, machine and precision"},
         "estimator_health": health,
         "surrogate": study,
         "batched": bstudy,

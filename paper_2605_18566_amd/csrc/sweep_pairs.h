@@ -72,6 +72,26 @@ __device__ __forceinline__ void swap_halves(bf16x8_t& a, bf16x8_t& b) {
 
 typedef const float __attribute__((address_space(4)))* const_f32_p;
 
+// Minimum of v[0..N) as a tree of three-way minima (depth log3 N instead of a
+// chain of N/2 dependent min3).
+template <int N>
+__device__ __forceinline__ float min_tree(const float* v) {
+  if constexpr (N == 1) {
+    return v[0];
+  } else if constexpr (N == 2) {
+    return fminf(v[0], v[1]);
+  } else {
+    constexpr int G = (N + 2) / 3;
+    float w[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int b = 3 * g;
+      w[g] = b + 2 < N ? fminf(fminf(v[b], v[b + 1]), v[b + 2]) : (b + 1 < N ? fminf(v[b], v[b + 1]) : v[b]);
+    }
+    return min_tree<G>(w);
+  }
+}
+
 template <int NM, int MP>
 __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qblock, int split) {
   constexpr int KS = NM / 16;
@@ -227,18 +247,18 @@ __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qb
           for (int k = 0; k < NSL; ++k) znext[k] = zr[k];
         }
         __builtin_amdgcn_sched_barrier(0);
-        float best;
+        float r2[MP];
         {
           const float y01 = fmaf(sg, zcur[1], us[1]);
-          best = fmaf(y00, y00, y01 * y01);
+          r2[0] = fmaf(y00, y00, y01 * y01);
         }
 #pragma unroll
         for (int k = 1; k < MP; ++k) {
           const float y0 = fmaf(sg, zcur[2 * k], us[2 * k]);
           const float y1 = fmaf(sg, zcur[2 * k + 1], us[2 * k + 1]);
-          best = fminf(best, fmaf(y0, y0, y1 * y1));
+          r2[k] = fmaf(y0, y0, y1 * y1);
         }
-        const float ell = __builtin_amdgcn_sqrtf(best) - A.dp.r;
+        const float ell = __builtin_amdgcn_sqrtf(min_tree<MP>(r2)) - A.dp.r;
         const float av = fmaf(-cl, ell, a0 - a[u]);
         if constexpr (decltype(masked)::value) {
           const int j = g0 + 8 * ((u & 15) / 4) + 4 * (u / 16) + (u & 3);
