@@ -808,8 +808,15 @@ struct SpecKey {
 
 // Samples per split in a batched launch: the batch as a whole fills the GPU,
 // so each problem is cut only into splits of about this many samples.
+// Batched sweeps run as persistent launches (resident blocks take work items
+// from a queue) unless HJG_BATCH_PERSISTENT=0 asks for one block per item.
+bool batched_persistent() {
+  const char* e = std::getenv("HJG_BATCH_PERSISTENT");
+  return !(e && e[0] == '0');
+}
+
 int batched_split_samples(const hjg_ctx* ctx) {
-  int ns = 16384;
+  int ns = 4096;
   const auto it = ctx->tuning.find("batch");
   if (it != ctx->tuning.end()) ns = it->second;
   if (const char* e = std::getenv("HJG_BATCH_SPLIT")) ns = std::atoi(e);
@@ -1087,9 +1094,17 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
         }
       launches.push_back(Launch{3, 0, o, cnt, k});
     }
+    // one work-queue head per sweep launch, after the item records
+    int n_sweeps = 0;
+    for (const Launch& L : launches) n_sweeps += L.kind == 1;
+    while (items.size() % 4) items.push_back(0);
+    const int64_t o_ctr = (int64_t)items.size();
+    items.resize(items.size() + std::max(n_sweeps, 1), 0);
     if ((rc = ensure(ctx, B.items, std::max<size_t>(items.size(), 4) * sizeof(int)))) return rc;
     HJG_HIP(hipMemcpy(B.items.p, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
     const int* d_items = (const int*)B.items.p;
+    int* d_ctr = (int*)B.items.p + o_ctr;
+    const bool persistent = batched_persistent();
 
     // ---- common tables (and their column means), generated once per plan
     for (int p = 0; p < P; ++p) {
@@ -1107,14 +1122,16 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
 
     // ---- record the whole uneven multi-problem Picard loop
     HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
+    hipError_t e = persistent ? launch_fill_ints(d_ctr, n_sweeps, 0, ctx->cap) : hipSuccess;
+    int sweep_i = 0;
     for (const Launch& L : launches) {
       if (e != hipSuccess) break;
       if (L.kind == 0) {
         ItemBatch<InitArgs> b{d_ia, (const int2*)(d_items + L.off), L.count};
         e = launch_init(ia[L.rep], ctx->cap, &b);
       } else if (L.kind == 1) {
-        SweepBatch b{d_sa, (const int4*)(d_items + L.off), L.count};
+        SweepBatch b{d_sa, (const int4*)(d_items + L.off), L.count, persistent ? d_ctr + sweep_i : nullptr};
+        ++sweep_i;
         e = launch_sweep(sa[L.rep], 0, pl[L.rep].bf16, ctx->cap, &b);
       } else if (L.kind == 2) {
         ItemBatch<FinalizeArgs> b{d_fa, (const int2*)(d_items + L.off), L.count};
@@ -1279,7 +1296,7 @@ extern "C" int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* 
   HJG_HIP(hipEventCreate(&sc.e0));
   HJG_HIP(hipEventCreate(&sc.e1));
   hipEvent_t e0 = sc.e0, e1 = sc.e1;
-  const int candidates[] = {4096, 8192, 16384, 32768, 65536};
+  const int candidates[] = {2048, 4096, 8192, 16384, 32768, 65536};
   double best = 1e300;
   int choice = 16384, rc = HJG_OK;
   for (int cand : candidates) {

@@ -116,6 +116,8 @@ struct SweepBatch {
   const SweepArgs* probs;
   const int4* items;
   int count;
+  int* counter;   // work-queue head (zero before the launch): a persistent grid
+                  // of resident blocks takes items in order; nullptr = one block per item
 };
 
 hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b = nullptr);
@@ -139,6 +141,17 @@ hipError_t launch_pair_coords(int m, int N, int64_t tstride, const void* table_b
 hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t G,
                                uint32_t* out, hipStream_t s);
 hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
+hipError_t launch_fill_ints(int* a, int64_t count, int value, hipStream_t s);
+
+// Item index a block of a persistent batched launch serves next: taken from
+// the work queue by one thread and shared through LDS; count or more = done.
+__device__ __forceinline__ int next_item(int* counter, int* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  const int b = *slot;
+  __syncthreads();
+  return b;
+}
 
 // Uniform hash grid over agent positions: cell (x, y, z) covers
 // [lo + (x, y, z) h, lo + (x+1, y+1, z+1) h); positions outside are clamped

@@ -288,6 +288,17 @@ hipError_t launch_pair_coords(int m, int N, int64_t tstride, const void* table_b
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kThreads) void fill_ints_kernel(int* a, int64_t count, int value) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) a[i] = value;
+}
+
+hipError_t launch_fill_ints(int* a, int64_t count, int value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_ints_kernel<<<(unsigned)((count + kThreads - 1) / kThreads), kThreads, 0, s>>>(a, count, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_zbar(int n, int N, int64_t tstride, int bf16, const void* table, double* zbar, hipStream_t s) {
   zbar_kernel<<<n, kThreads, 0, s>>>(N, tstride, bf16, table, zbar);
   return hipGetLastError();

@@ -16,6 +16,8 @@
 // part of the log-sum-exp merge).
 #pragma once
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "sweep_mfma.h"
 #include "sweep_pairs.h"
@@ -274,11 +276,16 @@ __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
 // Many problems in one launch: block b serves work item items[b] =
 // (problem, query block, sample split) with that problem's arguments.
 template <int DATUM, int NM, int MP, bool BF16>
-__global__ __launch_bounds__(kThreads) void sweep_crn_batched_kernel(const SweepArgs* probs, const int4* items) {
-  const int4 it = items[blockIdx.x];
-  const SweepArgs A = probs[it.x];
-  if (A.done && *A.done) return;
-  sweep_crn_block<DATUM, NM, MP, BF16>(A, it.y, it.z);
+__global__ __launch_bounds__(kThreads) void sweep_crn_batched_kernel(const SweepArgs* probs, const int4* items,
+                                                                     int count, int* counter) {
+  __shared__ int slot;
+  for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
+       b = counter ? next_item(counter, &slot) : count) {
+    const int4 it = items[b];
+    const SweepArgs& A = probs[it.x];
+    if (A.done && *A.done) continue;
+    sweep_crn_block<DATUM, NM, MP, BF16>(A, it.y, it.z);
+  }
 }
 
 // ------------------------------------------------------------------ fresh draws
@@ -339,13 +346,27 @@ __global__ __launch_bounds__(kThreads) void sweep_fresh_kernel(SweepArgs A) {
   write_partials<NM>(A, L, q, split, A.cv != 0);
 }
 
+// Grid of a batched launch: one block per item, or for a persistent launch
+// the blocks the device holds at once (never more than the items).
+template <class Kernel>
+unsigned batch_grid(Kernel kernel, int threads, const SweepBatch* b) {
+  if (!b->counter) return (unsigned)b->count;
+  int dev = 0, cus = 1, per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return (unsigned)b->count;
+  return (unsigned)std::max(1, std::min(b->count, cus * std::max(per_cu, 1)));
+}
+
 template <int DATUM, int NM, int MP>
 hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
   if (a.mfma) {
     if constexpr (NM >= 16 && DATUM == HJG_L_MIN_PAIR_DISKS) {
       if (fresh || !bf16) return hipErrorInvalidValue;
       if (b) {
-        sweep_pairs_batched_kernel<NM, MP><<<b->count, kPThreads, 0, s>>>(b->probs, b->items);
+        const unsigned g = batch_grid(sweep_pairs_batched_kernel<NM, MP>, kPThreads, b);
+        sweep_pairs_batched_kernel<NM, MP><<<g, kPThreads, 0, s>>>(b->probs, b->items, b->count, b->counter);
       } else {
         const dim3 grid((unsigned)((a.Q + kPQ - 1) / kPQ), (unsigned)a.splits);
         sweep_pairs_kernel<NM, MP><<<grid, kPThreads, 0, s>>>(a);
@@ -354,7 +375,8 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
     } else if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
       if (fresh || !bf16) return hipErrorInvalidValue;
       if (b) {
-        sweep_mfma_batched_kernel<DATUM, NM, MP><<<b->count, 256, 0, s>>>(b->probs, b->items);
+        const unsigned g = batch_grid(sweep_mfma_batched_kernel<DATUM, NM, MP>, 256, b);
+        sweep_mfma_batched_kernel<DATUM, NM, MP><<<g, 256, 0, s>>>(b->probs, b->items, b->count, b->counter);
       } else {
         const dim3 grid((unsigned)((a.Q + kMQ - 1) / kMQ), (unsigned)a.splits);
         sweep_mfma_kernel<DATUM, NM, MP><<<grid, 256, 0, s>>>(a);
@@ -366,8 +388,13 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
   }
   if (b) {
     if (fresh) return hipErrorInvalidValue;
-    if (bf16) sweep_crn_batched_kernel<DATUM, NM, MP, true><<<b->count, kThreads, 0, s>>>(b->probs, b->items);
-    else sweep_crn_batched_kernel<DATUM, NM, MP, false><<<b->count, kThreads, 0, s>>>(b->probs, b->items);
+    if (bf16) {
+      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, true>, kThreads, b);
+      sweep_crn_batched_kernel<DATUM, NM, MP, true><<<g, kThreads, 0, s>>>(b->probs, b->items, b->count, b->counter);
+    } else {
+      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, false>, kThreads, b);
+      sweep_crn_batched_kernel<DATUM, NM, MP, false><<<g, kThreads, 0, s>>>(b->probs, b->items, b->count, b->counter);
+    }
     return hipGetLastError();
   }
   const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads), (unsigned)a.splits);

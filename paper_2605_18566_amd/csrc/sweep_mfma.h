@@ -317,11 +317,16 @@ __global__ __launch_bounds__(256) void sweep_mfma_kernel(SweepArgs A) {
 }
 
 template <int DATUM, int NM, int MP>
-__global__ __launch_bounds__(256) void sweep_mfma_batched_kernel(const SweepArgs* probs, const int4* items) {
-  const int4 it = items[blockIdx.x];
-  const SweepArgs A = probs[it.x];
-  if (A.done && *A.done) return;
-  sweep_mfma_block<DATUM, NM, MP>(A, it.y, it.z);
+__global__ __launch_bounds__(256) void sweep_mfma_batched_kernel(const SweepArgs* probs, const int4* items, int count,
+                                                                 int* counter) {
+  __shared__ int slot;
+  for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
+       b = counter ? next_item(counter, &slot) : count) {
+    const int4 it = items[b];
+    const SweepArgs& A = probs[it.x];
+    if (A.done && *A.done) continue;
+    sweep_mfma_block<DATUM, NM, MP>(A, it.y, it.z);
+  }
 }
 
 }  // namespace hjg

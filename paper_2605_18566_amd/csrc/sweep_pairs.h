@@ -378,11 +378,15 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 
 template <int NM, int MP>
 __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(2))) void sweep_pairs_batched_kernel(
-    const SweepArgs* probs, const int4* items) {
-  const int4 it = items[blockIdx.x];
-  const SweepArgs A = probs[it.x];
-  if (A.done && *A.done) return;
-  sweep_pairs_block<NM, MP>(A, it.y, it.z);
+    const SweepArgs* probs, const int4* items, int count, int* counter) {
+  __shared__ int slot;
+  for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
+       b = counter ? next_item(counter, &slot) : count) {
+    const int4 it = items[b];
+    const SweepArgs& A = probs[it.x];
+    if (A.done && *A.done) continue;
+    sweep_pairs_block<NM, MP>(A, it.y, it.z);
+  }
 }
 
 }  // namespace hjg

@@ -63,7 +63,7 @@ def test_autotune_batched_choice_is_the_plan_it_runs(ctx, monkeypatch):
     args = ([bp.w.N for bp in batch], [bp.w.K for bp in batch], [bp.w.t for bp in batch])
     split, ms = autotune_batched(ctx, specs, xs, *args)
     print(f"[autotune batched] split={split} ms={ms:.3f}", flush=True)
-    assert split in (4096, 8192, 16384, 32768, 65536) and ms > 0
+    assert split in (2048, 4096, 8192, 16384, 32768, 65536) and ms > 0
     a = picard_sweep_batched(ctx, specs, xs, *args)
     va = a.v.clone()
     monkeypatch.setenv("HJG_BATCH_SPLIT", str(split))

@@ -131,3 +131,19 @@ def test_batched_stops_each_problem_on_its_own(ctx):
         one = picard_sweep(ctx, spec, to_dev(xs[p]), bp.w.t, bp.w.N, bp.w.K, tol=tol)
         assert out.iters[p] == one.iters_done
         assert np.all(out.resid_hist[p, out.iters[p]:] == 0.0)
+
+
+def test_persistent_launch_matches_one_block_per_item(monkeypatch):
+    # the work queue only changes which block serves an item, so results are
+    # bit-identical to the launch with one block per item
+    from paper_2605_18566_amd import Context
+    batch, xs = small_batch(P=10, trial=5)
+    outs = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HJG_BATCH_PERSISTENT", mode)
+        c = Context(0)
+        o = run_batched(c, batch, xs)
+        outs.append((o.v.clone(), o.grad.clone(), o.resid_hist.copy()))
+        c.close()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
