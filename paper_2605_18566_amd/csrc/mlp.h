@@ -43,6 +43,13 @@ hipError_t launch_row_sums(const __bf16* inT, int R, int C, int ld, float* out, 
 // dY = 2 w_j (Y - T) / B (bfloat16 and transposed); loss partial sums per block (float64)
 hipError_t launch_mse_loss(const float* Y, const float* T, const float* w, int B, int cols, int ld, __bf16* dY,
                            __bf16* dYT, double* block_loss, int* nblocks, hipStream_t s);
+// AdamW whose learning rate and bias corrections come from device step
+// counters ctr = {global step, optimizer steps done, batch of the epoch}.
+hipError_t launch_adamw_sched(float* w, const float* g, float* m, float* v, int64_t count, const int64_t* ctr,
+                              double lr_max, double lr_min, int64_t total, float beta1, float beta2, float eps,
+                              float wd, hipStream_t s);
+// ctr[0..2] += 1 (one thread)
+hipError_t launch_advance_counters(int64_t* ctr, hipStream_t s);
 hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int64_t count, float lr, float beta1,
                         float beta2, float eps, float wd, float bc1, float bc2, hipStream_t s);
 // bfloat16 copies of a float32 [rows][cols] matrix, plain and transposed
@@ -64,8 +71,9 @@ hipError_t launch_accumulate(const double* part, int count, double* acc, hipStre
 hipError_t launch_feature_stats(const float* base, int64_t stride, int nf, int64_t rows, float* mean, float* stdv,
                                 hipStream_t s);
 // batch gather: rows perm[r] of X_all [M][ld] and T_all [M][ldt]
+// rows perm[batch * B + r] (batch from device memory, or 0 when null)
 hipError_t launch_gather(const __bf16* X_all, const float* T_all, const int* perm, int B, int ld, int ldt,
-                         __bf16* Xb, __bf16* XbT, float* Tb, hipStream_t s);
+                         const int64_t* batch, __bf16* Xb, __bf16* XbT, float* Tb, hipStream_t s);
 // deterministic stream compaction of the states with flag != 0
 hipError_t launch_compact_count(const uint8_t* flags, int64_t Q, int* block_counts, int* nblocks, hipStream_t s);
 hipError_t launch_compact_scan(int* block_counts, int nblocks, int* total, hipStream_t s);

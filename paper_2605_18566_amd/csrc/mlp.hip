@@ -3,6 +3,8 @@
 // the surrogate-accelerated sweep's fallback.
 #include <algorithm>
 
+#include <cmath>
+
 #include "mlp.h"
 
 namespace hjg {
@@ -148,6 +150,34 @@ __global__ __launch_bounds__(256) void adamw_kernel(float* w, const float* g, fl
   w[i] = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
 }
 
+// AdamW with the step's learning rate and bias corrections formed on the
+// device from the step counters ctr = {global step k, optimizer steps done,
+// batch of the epoch}: cosine schedule lr_min + (lr - lr_min)(1 + cos(pi k/total))/2.
+__global__ __launch_bounds__(256) void adamw_sched_kernel(float* w, const float* g, float* m, float* v, int64_t count,
+                                                          const int64_t* ctr, double lr_max, double lr_min,
+                                                          int64_t total, float b1, float b2, float eps, float wd) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const double k = (double)ctr[0], step = (double)(ctr[1] + 1);
+  const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * k / (double)total)));
+  const float bc1 = (float)(1.0 - pow((double)b1, step)), bc2 = (float)(1.0 - pow((double)b2, step));
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / bc1, vh = vi / bc2;
+  w[i] = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+}
+
+__global__ void advance_counters_kernel(int64_t* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctr[0] += 1;
+    ctr[1] += 1;
+    ctr[2] += 1;
+  }
+}
+
 __global__ __launch_bounds__(256) void to_bf16_kernel(const float* W, int rows, int cols, __bf16* Wb, __bf16* WbT) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (int64_t)rows * cols) return;
@@ -240,8 +270,10 @@ __global__ __launch_bounds__(256) void feature_stats_kernel(const float* base, i
 }
 
 __global__ __launch_bounds__(256) void gather_kernel(const __bf16* X_all, const float* T_all, const int* perm, int B,
-                                                     int ld, int ldt, __bf16* Xb, __bf16* XbT, float* Tb) {
+                                                     int ld, int ldt, const int64_t* batch, __bf16* Xb, __bf16* XbT,
+                                                     float* Tb) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (batch) perm += *batch * B;
   if (i < (int64_t)B * ld) {
     const int r = (int)(i / ld), c = (int)(i % ld);
     const __bf16 x = X_all[(int64_t)perm[r] * ld + c];
@@ -351,6 +383,18 @@ hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int64_t co
   return hipGetLastError();
 }
 
+hipError_t launch_adamw_sched(float* w, const float* g, float* m, float* v, int64_t count, const int64_t* ctr,
+                              double lr_max, double lr_min, int64_t total, float beta1, float beta2, float eps,
+                              float wd, hipStream_t s) {
+  adamw_sched_kernel<<<nblk(count), 256, 0, s>>>(w, g, m, v, count, ctr, lr_max, lr_min, total, beta1, beta2, eps, wd);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_counters(int64_t* ctr, hipStream_t s) {
+  advance_counters_kernel<<<1, 64, 0, s>>>(ctr);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* WbT, hipStream_t s) {
   to_bf16_kernel<<<nblk((int64_t)rows * cols), 256, 0, s>>>(W, rows, cols, Wb, WbT);
   return hipGetLastError();
@@ -392,8 +436,9 @@ hipError_t launch_feature_stats(const float* base, int64_t stride, int nf, int64
 }
 
 hipError_t launch_gather(const __bf16* X_all, const float* T_all, const int* perm, int B, int ld, int ldt,
-                         __bf16* Xb, __bf16* XbT, float* Tb, hipStream_t s) {
-  gather_kernel<<<nblk((int64_t)B * std::max(ld, ldt)), 256, 0, s>>>(X_all, T_all, perm, B, ld, ldt, Xb, XbT, Tb);
+                         const int64_t* batch, __bf16* Xb, __bf16* XbT, float* Tb, hipStream_t s) {
+  gather_kernel<<<nblk((int64_t)B * std::max(ld, ldt)), 256, 0, s>>>(X_all, T_all, perm, B, ld, ldt, batch, Xb, XbT,
+                                                                      Tb);
   return hipGetLastError();
 }
 

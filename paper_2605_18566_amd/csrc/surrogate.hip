@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -78,6 +79,7 @@ struct hjg_surrogate {
   // batch workspace
   int64_t cap = 0;
   Buf X0, X0T, Y, T, dY, dYT, part, bl, acc, perm;
+  Buf ctr;                          // training step counters (device)
   std::vector<Buf> Z, X, XT;
   Buf dZ[2], dZT[2];
   // training set and sweep workspace
@@ -332,7 +334,8 @@ void hjg_surrogate_destroy(hjg_surrogate* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
   std::vector<Buf*> all = {&s->w, &s->g, &s->m, &s->v, &s->norm, &s->lw, &s->X0, &s->X0T, &s->Y, &s->T, &s->dY,
-                           &s->dYT, &s->part, &s->bl, &s->acc, &s->perm, &s->Xall, &s->Tall, &s->sv, &s->sg,
+                           &s->dYT, &s->part, &s->bl, &s->acc, &s->perm, &s->ctr, &s->Xall, &s->Tall, &s->sv,
+                           &s->sg,
                            &s->tq, &s->flags, &s->bcount, &s->total, &s->index, &s->xfb, &s->vfb, &s->gfb,
                            &s->dZ[0], &s->dZ[1], &s->dZT[0], &s->dZT[1]};
   for (auto& b : s->Wb) all.push_back(&b);
@@ -484,37 +487,74 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
   SG_HIP(launch_prep_targets(v, grad, s->n, M, s->out_p, nrm(s, 2), nrm(s, 3), (float*)s->Tall.p, st));
   const int64_t steps_per_epoch = M / B;
   const int64_t total = steps_per_epoch * cfg->epochs;
+  if ((rc = grow(s->ctr, 3 * sizeof(int64_t)))) return rc;
+  int64_t* ctr = (int64_t*)s->ctr.p;
+  // One training step: batch gather, forward, backward, AdamW (learning rate
+  // and bias corrections from the device counters), bf16 weight refresh,
+  // counter advance.  The first step runs directly (it also sizes every
+  // workspace); the rest replay it as a recorded graph.
+  auto train_step = [&](hipStream_t q) -> int {
+    int r;
+    SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, B, s->in_p,
+                         s->out_p, ctr + 2, (__bf16*)s->X0.p, (__bf16*)s->X0T.p, (float*)s->T.p, q));
+    if ((r = forward(s, B, true, q))) return r;
+    if ((r = backward(s, B, q))) return r;
+    SG_HIP(launch_adamw_sched((float*)s->w.p, (const float*)s->g.p, (float*)s->m.p, (float*)s->v.p, s->P, ctr,
+                              cfg->lr, cfg->lr_min, total, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps,
+                              (float)cfg->weight_decay, q));
+    if ((r = refresh_bf16(s, q))) return r;
+    SG_HIP(launch_advance_counters(ctr, q));
+    return HJG_OK;
+  };
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto release = [&](int code) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    return code;
+  };
+  const char* ng = std::getenv("HJG_NO_GRAPH");       // 1: every step launched directly (for comparison)
+  const bool use_graph = !(ng && ng[0] == '1');
   std::vector<int> perm(M);
   uint64_t seed = cfg->seed;
-  int64_t k = 0;
   for (int e = 0; e < cfg->epochs; ++e) {
     for (int64_t i = 0; i < M; ++i) perm[i] = (int)i;
     for (int64_t i = M - 1; i > 0; --i) {        // Fisher-Yates
       const int64_t j = (int64_t)(splitmix64(seed) % (uint64_t)(i + 1));
       std::swap(perm[i], perm[j]);
     }
-    SG_HIP(hipMemcpyAsync(s->perm.p, perm.data(), (size_t)M * 4, hipMemcpyHostToDevice, st));
-    SG_HIP(hipMemsetAsync(s->acc.p, 0, 8, st));
-    for (int64_t b = 0; b < steps_per_epoch; ++b, ++k) {
-      SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p + b * B, B,
-                           s->in_p, s->out_p, (__bf16*)s->X0.p, (__bf16*)s->X0T.p, (float*)s->T.p, st));
-      if ((rc = forward(s, B, true, st))) return rc;
-      if ((rc = backward(s, B, st))) return rc;
-      ++s->step;
-      const double lr = cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * (double)k / total));
-      const float bc1 = (float)(1.0 - std::pow(cfg->beta1, (double)s->step));
-      const float bc2 = (float)(1.0 - std::pow(cfg->beta2, (double)s->step));
-      SG_HIP(launch_adamw((float*)s->w.p, (const float*)s->g.p, (float*)s->m.p, (float*)s->v.p, s->P, (float)lr,
-                          (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps, (float)cfg->weight_decay, bc1, bc2,
-                          st));
-      if ((rc = refresh_bf16(s, st))) return rc;
+    const int64_t c0[3] = {e * steps_per_epoch, s->step + e * steps_per_epoch, 0};
+    if (hipMemcpyAsync(s->perm.p, perm.data(), (size_t)M * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ctr, c0, sizeof(c0), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(s->acc.p, 0, 8, st) != hipSuccess)
+      return release(fail(HJG_EHIP, "training: upload of the epoch's order failed"));
+    for (int64_t b = 0; b < steps_per_epoch; ++b) {
+      if (use_graph && !exec && (e > 0 || b > 0)) {
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+          return release(fail(HJG_EHIP, "training: graph capture could not start"));
+        rc = train_step(cap);
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        if (rc) return release(rc);
+        if (ec != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+          return release(fail(HJG_EHIP, "training: graph capture failed"));
+      }
+      if (exec) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) return release(fail(HJG_EHIP, "training: graph launch failed"));
+      } else if ((rc = train_step(st))) {
+        return release(rc);
+      }
     }
     double acc = 0.0;
-    SG_HIP(hipMemcpyAsync(&acc, s->acc.p, 8, hipMemcpyDeviceToHost, st));
-    SG_HIP(hipStreamSynchronize(st));   // the host buffer `perm` is reused next epoch
+    if (hipMemcpyAsync(&acc, s->acc.p, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)     // the host buffers are reused next epoch
+      return release(fail(HJG_EHIP, "training: loss read-back failed"));
     if (loss_hist) loss_hist[e] = acc / ((double)steps_per_epoch * B);
   }
-  return HJG_OK;
+  s->step += total;
+  return release(HJG_OK);
 }
 
 int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, int64_t Q, const float* x, double t,

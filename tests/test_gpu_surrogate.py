@@ -231,3 +231,27 @@ def test_trained_surrogate_gains_over_plain_sweep(ctx):
     assert rms(v) <= rms(plain.v)
     assert sur_pairs < 0.6 * plain_pairs
     sur.close()
+
+
+def test_recorded_training_steps_match_direct_launches(ctx, monkeypatch):
+    # training replays one recorded step graph (device step counters drive the
+    # batch, the learning rate and the bias corrections); the same training
+    # with every step launched directly must give identical parameters
+    from paper_2605_18566_amd import Surrogate, TrainConfig
+    n, M = 6, 4096
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-2, 2, (n, M)).astype(np.float32)
+    t = rng.uniform(0.2, 1.0, M).astype(np.float32)
+    v = np.sin(x[0]) * t
+    g = np.zeros((n, M), np.float32)
+    g[0] = np.cos(x[0]) * t
+    cfg = TrainConfig(epochs=3, batch=512, lr=3e-3, lr_min=1e-4, seed=4)
+    params, hists = [], []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("HJG_NO_GRAPH", mode)
+        sur = Surrogate(ctx, n, 64, 2, seed=2)
+        hists.append(sur.train(to_dev(x), to_dev(t), to_dev(v.astype(np.float32)), to_dev(g), cfg))
+        params.append(sur.get_params()[0])
+        sur.close()
+    np.testing.assert_array_equal(params[0], params[1])
+    np.testing.assert_array_equal(hists[0], hists[1])
