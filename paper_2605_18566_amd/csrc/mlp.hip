@@ -61,18 +61,22 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     __syncthreads();
   }
   const int n = n0 + wn * 32 + (lane & 31);
-  if (n >= g.N) return;
+  // transposed bf16 copies go through an LDS tile so their stores are
+  // coalesced rows of the transposed output
+  __shared__ __attribute__((aligned(16))) __bf16 Ts[kTN][kTM + 8];
+  const bool transposed = (EPI == EPI_BWD_DX) || (EPI == EPI_FWD_HIDDEN && g.outbT);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    const int m = m0 + wm * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-    if (m >= g.M) continue;
+    const int ml = wm * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+    const int m = m0 + ml;
+    if (m >= g.M || n >= g.N) continue;
     const float c = acc[v];
     if (EPI == EPI_FWD_HIDDEN) {
       const float z = c + g.bias[n];
       if (g.outf) g.outf[(int64_t)m * g.ldo + n] = z;
       const __bf16 s = (__bf16)(z * sigmoidf_(z));
       if (g.outb) g.outb[(int64_t)m * g.ldob + n] = s;
-      if (g.outbT) g.outbT[(int64_t)n * g.ldobT + m] = s;
+      if (g.outbT) Ts[n - n0][ml] = s;
     } else if (EPI == EPI_FWD_OUT) {
       g.outf[(int64_t)m * g.ldo + n] = c + g.bias[n];
     } else if (EPI == EPI_BWD_DX) {
@@ -80,9 +84,23 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       const float sg = sigmoidf_(z);
       const __bf16 d = (__bf16)(c * sg * (1.0f + z * (1.0f - sg)));
       g.outb[(int64_t)m * g.ldob + n] = d;
-      g.outbT[(int64_t)n * g.ldobT + m] = d;
+      Ts[n - n0][ml] = d;
     } else {
       g.outf[((int64_t)blockIdx.z * g.M + m) * g.ldo + n] = c;
+    }
+  }
+  if (transposed) {
+    __syncthreads();
+    for (int e = tid; e < kTN * (kTM / 8); e += 256) {
+      const int r = e / (kTM / 8), c = (e % (kTM / 8)) * 8;
+      const int nn = n0 + r, mm = m0 + c;
+      if (nn >= g.N || mm >= g.M) continue;
+      __bf16* dst = g.outbT + (int64_t)nn * g.ldobT + mm;
+      if (mm + 8 <= g.M && (((uintptr_t)dst) & 15) == 0) {
+        *reinterpret_cast<bf16x8*>(dst) = *reinterpret_cast<const bf16x8*>(&Ts[r][c]);
+      } else {
+        for (int q = 0; q < 8 && mm + q < g.M; ++q) dst[q] = Ts[r][c + q];
+      }
     }
   }
 }
