@@ -24,8 +24,11 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    Picard fixed point is "parity unpinned"
                                    against the viscous solution (the paper's
                                    quasi-linearisation defect is not computable)
-  model.hamiltonian (Dubins)     : brute-force max-min over control grids
+  model.hamiltonian (Dubins,     : brute-force max-min over control grids
+    multi-pursuer game)
   model.coefficient              : direct evaluation checks (sign, clip, eta)
+  model.datum (capture)          : a hand-built configuration; its gradient
+                                   against central differences
   knn.knn                        : a k-d tree (scipy) on random points, the
                                    unit-lattice closed form, duplicate points
                                    and float32 near-ties

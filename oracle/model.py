@@ -15,8 +15,8 @@ from typing import Optional
 
 import numpy as np
 
-HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator")
-DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear")
+HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator", "pursuit_evasion")
+DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear", "capture")
 
 
 @dataclass
@@ -26,8 +26,11 @@ class Problem:
     ham_p:   quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
              sign of the p2 term (+1 from the relative dynamics, -1 for the form
              the paper prints).  double_integrator: (u_max,).
+             pursuit_evasion: (a_evader, a_pursuer, u_max) for m = n/3 planar
+             agents (x, y, heading), the last one the evader.
     datum_p: ball: (k, r) -> ||y[:k]|| - r.  half_sqnorm: unused.
              min_pair_disks: (r,).  knn_balls: (r, K).  linear: (b,).
+             capture: (r,) -> min over pursuers of the distance to the evader, - r.
     datum_aux: linear: a[n].  knn_balls: neighbour positions [Q, K, 3].
     """
     n: int
@@ -81,6 +84,14 @@ def datum(pb: Problem, y: np.ndarray, q_aux: Optional[np.ndarray] = None) -> np.
     if kind == "linear":
         a = np.asarray(pb.datum_aux, dtype=np.float64)
         return y @ a + float(pb.datum_p[0])
+    if kind == "capture":
+        # target set of the multi-pursuer game (Section 3.2): some pursuer within
+        # r of the evader, the evader being the last agent
+        r = float(pb.datum_p[0])
+        m = pb.n // 3
+        e = 3 * (m - 1)
+        d2 = (y[..., 0:e:3] - y[..., e:e + 1]) ** 2 + (y[..., 1:e:3] - y[..., e + 1:e + 2]) ** 2
+        return np.sqrt(np.min(d2, axis=-1)) - r
     raise ValueError(f"unknown datum {kind}")
 
 
@@ -123,6 +134,22 @@ def datum_grad(pb: Problem, x: np.ndarray, aux_all: Optional[np.ndarray] = None)
         return g
     if kind == "linear":
         return np.broadcast_to(np.asarray(pb.datum_aux, dtype=np.float64), x.shape).copy()
+    if kind == "capture":
+        m = n // 3
+        e = 3 * (m - 1)
+        dx = x[:, 0:e:3] - x[:, e:e + 1]
+        dy = x[:, 1:e:3] - x[:, e + 1:e + 2]
+        d2 = dx * dx + dy * dy
+        j = np.argmin(d2, axis=1)                          # first minimum
+        rho = np.sqrt(d2[np.arange(Q), j])
+        safe = np.where(rho > 0, rho, 1.0)
+        gx = np.where(rho > 0, dx[np.arange(Q), j] / safe, 0.0)
+        gy = np.where(rho > 0, dy[np.arange(Q), j] / safe, 0.0)
+        g[np.arange(Q), 3 * j] = gx
+        g[np.arange(Q), 3 * j + 1] = gy
+        g[:, e] = -gx
+        g[:, e + 1] = -gy
+        return g
     raise ValueError(f"unknown datum {kind}")
 
 
@@ -146,6 +173,19 @@ def hamiltonian(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
             p1, p2, p3 = p[:, 3 * j], p[:, 3 * j + 1], p[:, 3 * j + 2]
             H += (p1 * (vp * np.cos(x3) - ve) + s * p2 * vp * np.sin(x3)
                   + w * np.abs(p1 * x2 - p2 * x1 - p3) - w * np.abs(p3))
+        return H
+    if kind == "pursuit_evasion":
+        # m planar agents (Section 3.2): x_i' = a_i cos th_i, y_i' = a_i sin th_i,
+        # th_i' = u_i with |u_i| <= u_max; the evader (last agent) maximises, the
+        # pursuers minimise, so the turn terms give +u_max|p_th| and -u_max|p_th|.
+        ae, ap, umax = (float(v) for v in pb.ham_p[:3])
+        m = pb.n // 3
+        H = np.zeros(x.shape[0])
+        for j in range(m):
+            a = ae if j == m - 1 else ap
+            th = x[:, 3 * j + 2]
+            H += a * (p[:, 3 * j] * np.cos(th) + p[:, 3 * j + 1] * np.sin(th))
+            H += (umax if j == m - 1 else -umax) * np.abs(p[:, 3 * j + 2])
         return H
     if kind == "double_integrator":
         # pos' = vel, vel' = u with ||u|| <= u_max, the agent maximising.
