@@ -72,8 +72,13 @@ enum hjg_ham {
                                 relative dynamics of the Dubins game in the
                                 appendix, s = -1 is the form printed there.      */
   HJG_H_ZERO = 2,            /* H = 0 (pure diffusion; c = +c_min)                     */
-  HJG_H_DOUBLE_INTEGRATOR = 3/* n = 6, x = (pos, vel): <p_pos, vel> + u_max |p_vel|;
+  HJG_H_DOUBLE_INTEGRATOR = 3,/* n = 6, x = (pos, vel): <p_pos, vel> + u_max |p_vel|;
                                 ham_p = {u_max}                                       */
+  HJG_H_PURSUIT_EVASION = 4  /* multi-pursuer single-evader game (Section 3.2): m = n/3
+                                planar agents (x, y, heading), the last the evader;
+                                sum_j a_j (p_xj cos th_j + p_yj sin th_j)
+                                + u_max |p_th,evader| - u_max sum_pursuers |p_th,j|;
+                                ham_p = {a_evader, a_pursuer, u_max}; 2 <= m <= 16 */
 };
 
 /* Terminal data l(y) (signed distance: negative inside the target set). */
@@ -85,7 +90,11 @@ enum hjg_datum {
   HJG_L_KNN_BALLS = 3,       /* min_j |y[0:3] - nb_j(q)| - r over the query's K
                                 neighbour positions; datum_p = {r, K}, K <= 8;
                                 datum_aux = device [K][3][Q]                          */
-  HJG_L_LINEAR = 4           /* <a, y> + b; datum_p = {b}; datum_aux = device a[n]     */
+  HJG_L_LINEAR = 4,          /* <a, y> + b; datum_p = {b}; datum_aux = device a[n]     */
+  HJG_L_CAPTURE = 5          /* min over pursuers j of |(y[3j], y[3j+1]) - evader
+                                position| - r, the evader being the last of the
+                                m = n/3 agents (capture set of the Section 3.2 game);
+                                datum_p = {r}; 2 <= m <= 16                           */
 };
 
 /* Where the draws come from. */

@@ -147,6 +147,12 @@ int check_problem(const hjg_problem* p) {
       for (int i = 0; i < 4; ++i)
         if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
       break;
+    case HJG_H_PURSUIT_EVASION:
+      if (p->n % 3 || p->n < 6 || p->n > 48) return fail(HJG_EINVAL, "the pursuit game needs n = 3m, 2 <= m <= 16");
+      for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
+      if (!(p->ham_p[2] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
+      break;
     case HJG_H_DOUBLE_INTEGRATOR:
       if (p->n != 6) return fail(HJG_EINVAL, "the double integrator needs n = 6");
       if (!(std::isfinite(p->ham_p[0]) && p->ham_p[0] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
@@ -165,6 +171,10 @@ int check_problem(const hjg_problem* p) {
     }
     case HJG_L_MIN_PAIR_DISKS:
       if (p->n % 3) return fail(HJG_EINVAL, "min_pair_disks needs n = 3m");
+      if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
+      break;
+    case HJG_L_CAPTURE:
+      if (p->n % 3 || p->n < 6 || p->n > 48) return fail(HJG_EINVAL, "capture needs n = 3m, 2 <= m <= 16");
       if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
       break;
     case HJG_L_KNN_BALLS: {
@@ -196,6 +206,7 @@ DatumP datum_params(const hjg_problem* p) {
   switch (p->datum) {
     case HJG_L_BALL: d.k = (int)p->datum_p[0]; d.r = (float)p->datum_p[1]; break;
     case HJG_L_MIN_PAIR_DISKS: d.r = (float)p->datum_p[0]; break;
+    case HJG_L_CAPTURE: d.r = (float)p->datum_p[0]; break;
     case HJG_L_KNN_BALLS: d.r = (float)p->datum_p[0]; d.k = (int)p->datum_p[1]; break;
     case HJG_L_LINEAR: d.r = (float)p->datum_p[0]; break;
     default: break;
@@ -254,7 +265,7 @@ int ilog2(int64_t v) {
 std::string sweep_key(const hjg_problem* p, int64_t Q, int N) {
   std::ostringstream k;
   k << "sweep " << (use_mfma(p) ? 1 : 0) << ' ' << p->datum << ' ' << n_bucket(p->n) << ' '
-    << (p->datum == HJG_L_MIN_PAIR_DISKS ? p->n / 3 : 0) << ' ' << p->sample_mode << ' ' << p->sample_bf16 << ' '
+    << ((p->datum == HJG_L_MIN_PAIR_DISKS || p->datum == HJG_L_CAPTURE) ? p->n / 3 : 0) << ' ' << p->sample_mode << ' ' << p->sample_bf16 << ' '
     << ilog2(Q) << ' ' << ilog2(N);
   return k.str();
 }
@@ -1060,7 +1071,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       for (int p = 0; p < P; ++p) {
         if (Ks[p] <= k) continue;
         const hjg_problem& pr = probs[p];
-        const SpecKey sk{pr.datum, n_bucket(pr.n), pr.datum == HJG_L_MIN_PAIR_DISKS ? pr.n / 3 : 0, pl[p].mfma,
+        const SpecKey sk{pr.datum, n_bucket(pr.n), (pr.datum == HJG_L_MIN_PAIR_DISKS || pr.datum == HJG_L_CAPTURE) ? pr.n / 3 : 0, pl[p].mfma,
                          pl[p].bf16};
         groups[sk].push_back(p);
       }

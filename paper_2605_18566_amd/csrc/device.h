@@ -71,7 +71,7 @@ struct DatumP {
   int kind;       // enum hjg_datum
   int n;          // state dimension
   int k;          // BALL: leading dims; KNN: neighbours
-  int m;          // MIN_PAIR_DISKS: pairs (n / 3)
+  int m;          // MIN_PAIR_DISKS: pairs; CAPTURE: agents (n / 3)
   float r;        // radius (BALL, MIN_PAIR_DISKS, KNN) or offset b (LINEAR)
   const float* aux;  // LINEAR: a[n]; KNN: [K][3][Q]
 };
@@ -141,6 +141,32 @@ __device__ inline float datum_and_grad(const DatumP& dp, const float* x, float* 
       if (rho > 0.f) { g[0] = b0 / rho; g[1] = b1 / rho; g[2] = b2 / rho; }
       return rho - dp.r;
     }
+    case HJG_L_CAPTURE: {
+      const int e = dp.m - 1;                        // the evader is the last agent
+      float ex = 0.f, ey = 0.f;
+#pragma unroll
+      for (int j = 0; j < NM / 3; ++j)
+        if (j == e) { ex = x[3 * j]; ey = x[3 * j + 1]; }
+      float best = INFINITY, bx = 0.f, by = 0.f;
+      int jb = 0;
+#pragma unroll
+      for (int j = 0; j < NM / 3; ++j) {
+        if (j < e) {
+          const float dx = x[3 * j] - ex, dy = x[3 * j + 1] - ey;
+          const float r2 = dx * dx + dy * dy;
+          if (r2 < best) { best = r2; jb = j; bx = dx; by = dy; }
+        }
+      }
+      const float rho = sqrtf(best);
+      if (rho > 0.f) {
+#pragma unroll
+        for (int j = 0; j < NM / 3; ++j) {
+          if (j == jb) { g[3 * j] = bx / rho; g[3 * j + 1] = by / rho; }
+          if (j == e) { g[3 * j] = -bx / rho; g[3 * j + 1] = -by / rho; }
+        }
+      }
+      return rho - dp.r;
+    }
     case HJG_L_LINEAR:
     default: {
       float s = dp.r;
@@ -172,6 +198,21 @@ __device__ inline float hamiltonian(const HamP& hp, const float* x, const float*
           float s3, c3;
           sincosf(x3, &s3, &c3);
           H += p1 * (vp * c3 - ve) + sg * p2 * vp * s3 + w * fabsf(p1 * x2 - p2 * x1 - p3) - w * fabsf(p3);
+        }
+      }
+      return H;
+    }
+    case HJG_H_PURSUIT_EVASION: {
+      const float ae = hp.p[0], ap = hp.p[1], um = hp.p[2];
+      const int e = hp.n / 3 - 1;
+      float H = 0.f;
+#pragma unroll
+      for (int j = 0; j < NM / 3; ++j) {
+        if (3 * j < hp.n) {
+          float s3, c3;
+          sincosf(x[3 * j + 2], &s3, &c3);
+          const bool ev = j == e;
+          H += (ev ? ae : ap) * (p[3 * j] * c3 + p[3 * j + 1] * s3) + (ev ? um : -um) * fabsf(p[3 * j + 2]);
         }
       }
       return H;

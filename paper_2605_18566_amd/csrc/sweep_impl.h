@@ -132,6 +132,21 @@ __device__ __forceinline__ float pair_log2w(const PairConst<DATUM, NM>& P, const
       tz = fmaf(z2, P.tl[3 * j + 2], tz);
     }
     ell = __builtin_amdgcn_sqrtf(best) - dp.r;
+  } else if constexpr (DATUM == HJG_L_CAPTURE) {
+    // MP agents, the last the evader: min over pursuers of |y_j - y_evader|
+    constexpr int E = MP - 1;
+    const float ye0 = fmaf(P.sg, zf(3 * E), P.u[3 * E]);
+    const float ye1 = fmaf(P.sg, zf(3 * E + 1), P.u[3 * E + 1]);
+    float best = INFINITY;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const float y0 = fmaf(P.sg, zf(3 * j), P.u[3 * j]) - ye0;
+      const float y1 = fmaf(P.sg, zf(3 * j + 1), P.u[3 * j + 1]) - ye1;
+      best = fminf(best, fmaf(y0, y0, y1 * y1));
+    }
+#pragma unroll
+    for (int d = 0; d < 3 * MP; ++d) tz = fmaf(zf(d), P.tl[d], tz);
+    ell = __builtin_amdgcn_sqrtf(best) - dp.r;
   } else if constexpr (DATUM == HJG_L_KNN_BALLS) {
     const float z0 = zf(0), z1 = zf(1), z2 = zf(2);
     const float s0 = P.sg * z0, s1 = P.sg * z1, s2 = P.sg * z2;
@@ -419,9 +434,33 @@ hipError_t launch_pairs_exact(const SweepArgs& a, int fresh, int bf16, hipStream
   return launch_sweep_dn<HJG_L_MIN_PAIR_DISKS, NM, M>(a, fresh, bf16, s, b);
 }
 
+template <int NM, int M>
+hipError_t launch_capture_exact(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
+  return launch_sweep_dn<HJG_L_CAPTURE, NM, M>(a, fresh, bf16, s, b);
+}
+
 template <int DATUM>
 hipError_t launch_sweep_d(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
-  if constexpr (DATUM == HJG_L_KNN_BALLS) {
+  if constexpr (DATUM == HJG_L_CAPTURE) {
+    switch (a.n / 3) {
+      case 2: return launch_capture_exact<8, 2>(a, fresh, bf16, s, b);
+      case 3: return launch_capture_exact<16, 3>(a, fresh, bf16, s, b);
+      case 4: return launch_capture_exact<16, 4>(a, fresh, bf16, s, b);
+      case 5: return launch_capture_exact<16, 5>(a, fresh, bf16, s, b);
+      case 6: return launch_capture_exact<32, 6>(a, fresh, bf16, s, b);
+      case 7: return launch_capture_exact<32, 7>(a, fresh, bf16, s, b);
+      case 8: return launch_capture_exact<32, 8>(a, fresh, bf16, s, b);
+      case 9: return launch_capture_exact<32, 9>(a, fresh, bf16, s, b);
+      case 10: return launch_capture_exact<32, 10>(a, fresh, bf16, s, b);
+      case 11: return launch_capture_exact<48, 11>(a, fresh, bf16, s, b);
+      case 12: return launch_capture_exact<48, 12>(a, fresh, bf16, s, b);
+      case 13: return launch_capture_exact<48, 13>(a, fresh, bf16, s, b);
+      case 14: return launch_capture_exact<48, 14>(a, fresh, bf16, s, b);
+      case 15: return launch_capture_exact<48, 15>(a, fresh, bf16, s, b);
+      case 16: return launch_capture_exact<48, 16>(a, fresh, bf16, s, b);
+      default: return hipErrorInvalidValue;
+    }
+  } else if constexpr (DATUM == HJG_L_KNN_BALLS) {
     return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s, b);
   } else if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
     switch (a.n / 3) {

@@ -40,7 +40,7 @@ constexpr int kMS = 128;                // samples per LDS round
 // unused otherwise; a compile-time count keeps the datum loop free of branches.
 template <int DATUM, int NM, int MP>
 constexpr int mfma_ndat() {
-  return DATUM == HJG_L_MIN_PAIR_DISKS ? 2 * MP : (DATUM == HJG_L_LINEAR ? 0 : NM);
+  return (DATUM == HJG_L_MIN_PAIR_DISKS || DATUM == HJG_L_CAPTURE) ? 2 * MP : (DATUM == HJG_L_LINEAR ? 0 : NM);
 }
 template <int DATUM, int NM, int MP>
 constexpr int mfma_ps() {   // row stride of the float32 table: multiple of 4, +4 against bank conflicts
@@ -57,7 +57,7 @@ struct alignas(16) MfmaLds {
 // Coordinate slot of dimension d in the float32 datum table, or -1.
 template <int DATUM>
 __device__ __forceinline__ int datum_slot(const DatumP& dp, int d) {
-  if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) return (d % 3 < 2) ? 2 * (d / 3) + d % 3 : -1;
+  if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS || DATUM == HJG_L_CAPTURE) return (d % 3 < 2) ? 2 * (d / 3) + d % 3 : -1;
   else if constexpr (DATUM == HJG_L_BALL) return d < dp.k ? d : -1;
   else if constexpr (DATUM == HJG_L_HALF_SQNORM) return d;
   else return -1;
@@ -74,6 +74,18 @@ __device__ __forceinline__ float mfma_ell(const float* ud, const float* sd, floa
     for (int k = 0; k < MP; ++k) {
       const float y0 = fmaf(sg, zr[2 * k], ud[2 * k]);
       const float y1 = fmaf(sg, zr[2 * k + 1], ud[2 * k + 1]);
+      best = fminf(best, fmaf(y0, y0, y1 * y1));
+    }
+    return __builtin_amdgcn_sqrtf(best) - dp.r;
+  } else if constexpr (DATUM == HJG_L_CAPTURE) {
+    constexpr int E = MP - 1;                       // the evader is the last agent
+    const float ye0 = fmaf(sg, zr[2 * E], ud[2 * E]);
+    const float ye1 = fmaf(sg, zr[2 * E + 1], ud[2 * E + 1]);
+    float best = INFINITY;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const float y0 = fmaf(sg, zr[2 * k], ud[2 * k]) - ye0;
+      const float y1 = fmaf(sg, zr[2 * k + 1], ud[2 * k + 1]) - ye1;
       best = fminf(best, fmaf(y0, y0, y1 * y1));
     }
     return __builtin_amdgcn_sqrtf(best) - dp.r;

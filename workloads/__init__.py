@@ -128,6 +128,22 @@ def flock_agents(M: int = 100000, trial: int = 0, extent: Optional[float] = None
     return np.concatenate([pos, vel], 1).astype(np.float32)
 
 
+# The paper's 45-dimensional multi-pursuer single-evader game (Section 3.2,
+# Table 2): 14 pursuers and one evader (the last agent), capture radius 1.5,
+# three speed regimes; delta = 0.08 (nu = 0.04) as in the paper's 3D games,
+# N = 20,000 draws (the 7.2 MB per iteration the paper reports at n = 45),
+# K = 15 iterations, 1,600 evaluation states (a 40 x 40 slice's count) with
+# positions in a 20 x 20 square and headings in [-pi, pi), t = 1.
+def pursuit_box(m: int, half: float = 10.0):
+    return tuple([(-half, half), (-half, half), (-PI, PI)] * m)
+
+
+PURSUIT_REGIMES = {"evader_faster": (2.0, 1.0), "equal_speed": (1.0, 1.0), "pursuers_faster": (1.0, 2.0)}
+C6 = Workload("c6_pursuit15_n45", n=45, ham="pursuit_evasion", ham_p=(2.0, 1.0, 1.0), datum="capture",
+              datum_p=(1.5,), nu=0.04, t=1.0, Q=1600, N=20000, K=15, box=pursuit_box(15), tilt=True,
+              sample_mode="crn_step", sample_bf16=True, cfg=7, tube=True)
+
+
 def horizons(w: Workload):
     """Time-to-go of each horizon: t_j = j T / S_t, j = 1..S_t."""
     return [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
