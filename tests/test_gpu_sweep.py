@@ -88,10 +88,10 @@ CASES = {
     "mfma_quad_ball_n16_k3": (dict(workloads.C1.problem_fields(), n=16, datum_p=(3, 1.0), sample_mode="crn_step",
                                    sample_bf16=True, tilt=True, grad_cv=True), 257, 999),
     # the multi-pursuer game: vector-ALU (n < 16, fp32, fresh) and matrix-core paths
-    "pursuit_n9_fp32": (dict(workloads.C6.problem_fields(), n=9, sample_bf16=False), 700, 3001),
+    "pursuit_n9_fp32": (dict(workloads.C6.problem_fields(), n=9, sample_bf16=False, tilt=True), 700, 3001),
     "pursuit_n9_fresh": (dict(workloads.C6.problem_fields(), n=9, sample_mode="fresh", sample_bf16=False), 400, 2000),
     "pursuit_n45_fp32_valu": (dict(workloads.C6.problem_fields(), sample_bf16=False), 300, 1500),
-    "mfma_pursuit_n45": (dict(workloads.C6.problem_fields()), 333, 2000 + 5),
+    "mfma_pursuit_n45": (dict(workloads.C6.problem_fields(), tilt=True), 333, 2000 + 5),
     "mfma_pursuit_n18_slow_evader": (dict(workloads.C6.problem_fields(), n=18, ham_p=(1.0, 2.0, 1.0)), 400, 1800),
 }
 

@@ -139,8 +139,11 @@ def pursuit_box(m: int, half: float = 10.0):
 
 
 PURSUIT_REGIMES = {"evader_faster": (2.0, 1.0), "equal_speed": (1.0, 1.0), "pursuers_faster": (1.0, 2.0)}
+# The plain estimator (no shift): with the Laplace shift the importance
+# weights of this game degenerate (median ESS ~ 3 of 4,096) and the iteration
+# does not contract; without it the median ESS is ~ 1,400.
 C6 = Workload("c6_pursuit15_n45", n=45, ham="pursuit_evasion", ham_p=(2.0, 1.0, 1.0), datum="capture",
-              datum_p=(1.5,), nu=0.04, t=1.0, Q=1600, N=20000, K=15, box=pursuit_box(15), tilt=True,
+              datum_p=(1.5,), nu=0.04, t=1.0, Q=1600, N=20000, K=15, box=pursuit_box(15), tilt=False,
               sample_mode="crn_step", sample_bf16=True, cfg=7, tube=True)
 
 
