@@ -301,9 +301,16 @@ def flock_study(ctx, stream):
     slots = alu_slots_knn_pair(k, w.n)
     per_launch = kernel_ms / max(launches, 1)
     achieved = slots * w.Q * w.N / (per_launch * 1e-3)
+    # algorithmic bytes of build + search: positions read twice (24), cell
+    # ids and ranks written and read (16), cell-ordered records written and
+    # read (32), k neighbour indices and positions written (16k)
+    knn_bytes = w.Q * (24 + 16 + 32 + 16 * k)
     return {"workload": f"{w.name}: {w.Q} agents, 7-NN union-of-balls target (r = 0.2), double integrator, "
                         f"nu = {w.nu}, {len(hs)} horizons x K = {w.K}, N = {w.N} bf16 common draws, tube coefficient",
             "knn_grid_ms": knn_ms,
+            "knn_grid_algorithmic_GBps": knn_bytes / (knn_ms * 1e-3) / 1e9,
+            "knn_grid_note": "one finiteness check (a stream synchronisation) and six small launches for 100,000 "
+                             "agents: latency-bound, far from the 8 TB/s HBM roofline",
             "sweep_seconds_all_horizons": dt,
             "query_samples_per_s": pairs / dt,
             "pair_loop": {"bound": "alu", "alu_slots_per_pair": slots, "kernel_ms_per_launch": per_launch,
