@@ -320,6 +320,55 @@ def flock_study(ctx, stream):
                                     "frac_v_below_zero": float(np.mean(last.v.cpu().numpy() < 0))}}
 
 
+def small_configs_study(ctx, stream):
+    """The two small configurations: C1 (n = 2, fresh draws, one iteration)
+    and C2 (n = 3 relative Dubins, 10 horizons x K = 5, N = 65,536 common
+    draws), both on the vector-ALU pair loop."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, picard_sweep, value_grad
+    out = {}
+    with torch.cuda.stream(stream):
+        w = workloads.C1
+        x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to("cuda:0")
+        spec = ProblemSpec(**w.problem_fields())
+        c = torch.full((w.Q,), 1.0 / (2.0 * w.nu), dtype=torch.float32, device="cuda:0")
+        value_grad(ctx, spec, x, w.t, w.N, c, stream=stream)
+        reps = 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            value_grad(ctx, spec, x, w.t, w.N, c, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["c1_quadratic_disk_n2"] = {"Q": w.Q, "N": w.N, "K": w.K, "draws": "fresh Philox per query",
+                                       "seconds_per_sweep": dt, "query_samples_per_s": w.Q * w.N / dt}
+        w = workloads.C2
+        x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to("cuda:0")
+        spec = ProblemSpec(**w.problem_fields())
+        hs = workloads.horizons(w)
+        for j, t in enumerate(hs):                              # record the graphs
+            picard_sweep(ctx, spec, x, t, w.N, w.K, time_step=j + 1, host_outputs=False, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j, t in enumerate(hs):
+            picard_sweep(ctx, spec, x, t, w.N, w.K, time_step=j + 1, host_outputs=False, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.set_timing(True)
+        picard_sweep(ctx, spec, x, hs[-1], w.N, w.K, time_step=len(hs), host_outputs=False, stream=stream)
+        ms, nl = ctx.sweep_time()
+        ctx.set_timing(False)
+        slots = alu_slots_per_pair(w.datum, w.n) + 2 * w.n      # contractions on the vector ALUs at n = 3
+        out["c2_dubins_n3"] = {"Q": w.Q, "N": w.N, "K": w.K, "horizons": len(hs), "seconds_all_horizons": dt,
+                               "query_samples_per_s": w.Q * w.N * w.K * len(hs) / dt,
+                               "pair_loop": {"kernel_ms_per_launch": ms / max(nl, 1), "alu_slots_per_pair": slots,
+                                             "frac": slots * w.Q * w.N / (ms / max(nl, 1) * 1e-3) / VALU_PEAK}}
+    return out
+
+
 def pursuit_study(ctx, stream):
     """The paper's 45-dimensional multi-pursuer single-evader game (Table 2):
     three speed regimes, K = 15 Picard iterations, N = 20,000 draws, 1,600
@@ -391,6 +440,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch study")
     ap.add_argument("--no-flock", action="store_true", help="skip the flock study")
     ap.add_argument("--no-pursuit", action="store_true", help="skip the 45-dimensional pursuit-game study")
+    ap.add_argument("--no-small", action="store_true", help="skip the C1/C2 small-configuration study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -472,6 +522,9 @@ def main():
     pstudy = None
     if not args.no_pursuit:
         pstudy = pursuit_study(ctx, stream)
+    sstudy = None
+    if not args.no_small:
+        sstudy = small_configs_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -514,6 +567,7 @@ def main():
         "batched": bstudy,
         "flock": fstudy,
         "pursuit_game": pstudy,
+        "small_configs": sstudy,
     }
     print(json.dumps(line))
 
