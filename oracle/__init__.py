@@ -24,6 +24,13 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    Picard fixed point is "parity unpinned"
                                    against the viscous solution (the paper's
                                    quasi-linearisation defect is not computable)
+  estimator.tube_step            : semigroup step reproduces the closed form of
+                                   the exact quadratic case at the later time;
+                                   from t_prev = 0 with the terminal datum it
+                                   is bit-identical to estimator.picard
+  mlp.forward_bf16_storage /     : reduces to the plain forward when rounding
+    value_at, round_bf16           is the identity; rounding ties by hand and
+                                   against the draw generator's rounding
   model.hamiltonian (Dubins,     : brute-force max-min over control grids
     multi-pursuer game)
   model.coefficient              : direct evaluation checks (sign, clip, eta)

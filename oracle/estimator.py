@@ -29,7 +29,7 @@ p^(k+1) = Dv^(k+1), and stop once ||v^(k+1) - v^(k)|| / ||v^(k)|| < tol
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Optional
+from typing import Callable, Optional
 
 import numpy as np
 
@@ -61,10 +61,12 @@ def draws_for(pb: model.Problem, queries: np.ndarray, time_step: int, iteration:
 
 def value_grad(pb: model.Problem, x: np.ndarray, t: float, N: int, c: np.ndarray,
                theta: Optional[np.ndarray] = None, time_step: int = 0, iteration: int = 0,
-               z: Optional[np.ndarray] = None, chunk_bytes: float = 2 ** 27) -> Estimate:
+               z: Optional[np.ndarray] = None, chunk_bytes: float = 2 ** 27,
+               datum_fn: Optional[Callable[[np.ndarray], np.ndarray]] = None) -> Estimate:
     """One frozen-coefficient sweep at all queries x[Q, n] (the estimators above).
 
     z, if given, overrides the generator: shape [n, N] (shared) or [Q, n, N].
+    datum_fn, if given, replaces the terminal datum: y [Qc, N, n] -> l [Qc, N].
     """
     x = np.asarray(x, dtype=np.float64)
     Q, n = x.shape
@@ -89,8 +91,11 @@ def value_grad(pb: model.Problem, x: np.ndarray, t: float, N: int, c: np.ndarray
         zt = np.transpose(zc, (0, 2, 1))                               # [Qc, N, n]
         th = theta[qs]
         y = x[qs, None, :] + th[:, None, :] + sigma * zt               # [Qc, N, n]
-        aux = None if pb.datum != "knn_balls" else np.asarray(pb.datum_aux)[qs]
-        ell = model.datum(pb, y, aux)                                  # [Qc, N]
+        if datum_fn is None:
+            aux = None if pb.datum != "knn_balls" else np.asarray(pb.datum_aux)[qs]
+            ell = model.datum(pb, y, aux)                              # [Qc, N]
+        else:
+            ell = np.asarray(datum_fn(y), dtype=np.float64)
         a = (-c[qs, None] * ell
              - np.sum(th * th, axis=1)[:, None] / (2.0 * sigma ** 2)
              - np.einsum("qin,qn->qi", zt, th) / sigma)
@@ -161,3 +166,44 @@ def datum_at(pb: model.Problem, x: np.ndarray) -> np.ndarray:
     """l at the evaluation states themselves (v^(0) = g in Algorithm 1)."""
     aux = np.asarray(pb.datum_aux) if pb.datum == "knn_balls" else None
     return model.datum(pb, np.asarray(x, dtype=np.float64)[:, None, :], aux)[:, 0]
+
+
+def tube_step(pb: model.Problem, x: np.ndarray, t_prev: float, dt: float, N: int, K: int,
+              datum_fn: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, p0: np.ndarray,
+              tol: float = 0.0, time_step: int = 0, z: Optional[np.ndarray] = None) -> PicardResult:
+    """One step of time marching in semigroup form.
+
+    The value at t_prev + dt solves the same viscous equation over [t_prev,
+    t_prev + dt] with v(t_prev, .) as its initial datum (the solution operator
+    of the equation is a semigroup; Algorithm 1 needs only a datum and a
+    horizon).  So this is Algorithm 1 with the horizon dt (sigma^2 = delta dt),
+    the datum y -> v(t_prev, y) given by datum_fn, and the Picard loop started
+    from the previous value and its gradient at the states: v^(0) = v0,
+    p^(0) = p0 (the "Fix" step of Algorithm 1 with v(t_prev, .) in place of l).
+    With the tube flag of the problem the coefficient is frozen from
+    min{0, H}, as in the tube equation.  z, if given, overrides the draws as
+    in value_grad.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    Q, n = x.shape
+    sigma = np.sqrt(pb.delta * dt)
+    v_prev = np.asarray(v0, dtype=np.float64).copy()
+    p = np.asarray(p0, dtype=np.float64).copy()
+    hist = []
+    est = None
+    c = theta = None
+    rq = np.zeros(Q)
+    for k in range(K):
+        c = model.coefficient(pb, x, p)
+        theta = model.tilt(pb, sigma, c, p)
+        est = value_grad(pb, x, dt, N, c, theta, time_step=time_step, iteration=k, z=z, datum_fn=datum_fn)
+        dv = est.v - v_prev
+        den = np.sqrt(np.sum(v_prev ** 2))
+        r = np.sqrt(np.sum(dv ** 2)) / den if den > 0 else np.sqrt(np.sum(dv ** 2))
+        hist.append(r)
+        rq = np.abs(dv) / np.maximum(np.abs(v_prev), v_floor(pb, dt))
+        v_prev = est.v
+        p = est.grad
+        if r < tol:
+            break
+    return PicardResult(est.v, est.grad, c, est.ess, rq > tol, np.array(hist), len(hist), est.lmax, theta)

@@ -72,3 +72,42 @@ def predict(params, xt, in_mean, in_std, out_mean, out_std):
     """Raw (x, t) rows -> raw (v, Dv) rows."""
     Y, _ = forward(params, normalise(xt, in_mean, in_std))
     return Y * out_std + out_mean
+
+
+def round_bf16(a):
+    """Round float64 values to the nearest bfloat16 (8 significant bits, ties
+    to even), returned as float64 (normal range only)."""
+    m, e = np.frexp(np.asarray(a, dtype=np.float64))
+    return np.ldexp(np.round(m * 256.0), e - 8)
+
+
+def forward_bf16_storage(params, X):
+    """Forward pass with the storage rounding of a bfloat16 network: weights,
+    inputs and every hidden activation rounded to bfloat16; products, sums,
+    biases and SiLU in float64; the output layer is not rounded."""
+    h = round_bf16(X)
+    L = len(params)
+    for li, (W, b) in enumerate(params):
+        z = h @ round_bf16(W).T + b
+        h = round_bf16(silu(z)) if li < L - 1 else z
+    return h
+
+
+def value_at(params, norm, y, t):
+    """Value head of the network at states y [..., n] and time t (raw units).
+
+    norm: [4][n + 1] (input mean, input std, output mean, output std)."""
+    y = np.asarray(y, dtype=np.float64)
+    shape = y.shape[:-1]
+    rows = y.reshape(-1, y.shape[-1])
+    xt = np.concatenate([rows, np.full((rows.shape[0], 1), float(t))], axis=1)
+    out = forward_bf16_storage(params, (xt - norm[0]) / norm[1])
+    return (out[:, 0] * norm[3][0] + norm[2][0]).reshape(shape)
+
+
+def value_grad_at(params, norm, x, t):
+    """(v, Dv) outputs of the network at x [Q, n], time t (raw units)."""
+    x = np.asarray(x, dtype=np.float64)
+    xt = np.concatenate([x, np.full((x.shape[0], 1), float(t))], axis=1)
+    out = forward_bf16_storage(params, (xt - norm[0]) / norm[1]) * norm[3] + norm[2]
+    return out[:, 0], out[:, 1:]
