@@ -372,6 +372,32 @@ int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* probl
                         int32_t K_s, int32_t N_fb, int32_t K_fb, double tol,
                         uint32_t time_step, float* v, float* grad,
                         uint8_t* fell_back, int64_t* n_fallback, void* hip_stream);
+/* One step of time marching, the trained surrogate serving as the datum
+ * (semigroup form of the viscous equation; tube equation HJI-RCBRT-Visc when
+ * problem->tube is set).  The value at t_prev + dt solves the same equation
+ * over [t_prev, t_prev + dt] from v(t_prev, .), so this is Algorithm 1 with
+ * the horizon dt (sigma^2 = 2 nu dt) and the datum y -> v_S(y, t_prev), the
+ * surrogate's value output at the previous time:
+ *   v^(0) = v_S(x, t_prev), p^(0) = Dv_S(x, t_prev) (the surrogate's gradient
+ *   output); for k < K: c and theta frozen from p^(k) as in hjg_picard_sweep;
+ *   y_i = x + theta + sigma z_i; l_i = v_S(y_i, t_prev) from one forward pass
+ *   of the network over the rows (query, sample) of a query chunk (up to 2^21
+ *   rows per pass); the estimators, residual and stop rule of
+ *   hjg_picard_sweep.
+ * Draws: the common table of (problem, time_step) (sample_mode must be
+ * HJG_S_CRN_STEP, float32 or bfloat16); N in [1, 2^21]; K in [1, 255].
+ * problem->datum and datum_p must be valid but are not used.  x device
+ * [n][Q]; v [Q], grad [n][Q] device out; c_out [Q] and ess [Q] device out or
+ * NULL; resid_hist host [K] or NULL (zero past the last iteration);
+ * *iters_done host or NULL.  problem->n must equal the surrogate's n.
+ * Synchronises the stream after every iteration (the stop test is read on the
+ * host).  Errors: HJG_EINVAL (arguments), HJG_EUNSUPPORTED (fresh draws),
+ * HJG_ENOMEM, HJG_EHIP. */
+int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* problem,
+                            int64_t Q, const float* x, double t_prev, double dt,
+                            int32_t N, int32_t K, double tol, uint32_t time_step,
+                            float* v, float* grad, float* c_out, float* ess,
+                            double* resid_hist, int32_t* iters_done, void* hip_stream);
 
 /*
  * Kernel timing (profiling hook).  With timing enabled, every launch of the

@@ -431,3 +431,26 @@ def surrogate_sweep(ctx: Context, sur: Surrogate, spec: ProblemSpec, x: torch.Te
                                          int(K_s), int(N_fb), int(K_fb), float(tol), int(time_step), _ptr(v),
                                          _ptr(g), _ptr(fb), C.byref(nfb), _stream(stream)))
     return v, g, fb, int(nfb.value)
+
+
+def surrogate_tube_step(ctx: Context, sur: Surrogate, spec: ProblemSpec, x: torch.Tensor, t_prev: float, dt: float,
+                        N: int, K: int, tol: float = 0.0, time_step: int = 0, stream=None) -> PicardOut:
+    """One time-marching step with the surrogate as the datum (hjg_surrogate_tube_step):
+    the value at t_prev + dt from v_S(., t_prev).  Returns a PicardOut (flags unused)."""
+    _require_cuda(x, "x")
+    n, Q = x.shape
+    if n != spec.n:
+        raise ValueError("x must have shape [n, Q]")
+    dev = x.device
+    out = PicardOut(torch.empty(Q, dtype=torch.float32, device=dev), torch.empty((n, Q), dtype=torch.float32, device=dev),
+                    torch.empty(Q, dtype=torch.float32, device=dev), torch.empty(Q, dtype=torch.float32, device=dev),
+                    torch.zeros(Q, dtype=torch.uint8, device=dev), np.zeros(K), 0, 0)
+    hist = (C.c_double * K)()
+    iters = C.c_int32(0)
+    p = spec.to_c()
+    check(_lib.lib().hjg_surrogate_tube_step(ctx.handle, sur.handle, C.byref(p), Q, _ptr(x), float(t_prev), float(dt),
+                                             int(N), int(K), float(tol), int(time_step), _ptr(out.v), _ptr(out.grad),
+                                             _ptr(out.c), _ptr(out.ess), hist, C.byref(iters), _stream(stream)))
+    out.resid_hist = np.array(list(hist))
+    out.iters_done = int(iters.value)
+    return out

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "hjg.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace hjg;
@@ -363,6 +364,15 @@ int check_common(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, double t, int32_
 }
 
 }  // namespace
+
+namespace hjg {
+namespace detail {
+int check_problem(const hjg_problem* p) { return ::check_problem(p); }
+DatumP datum_params(const hjg_problem* p) { return ::datum_params(p); }
+HamP ham_params(const hjg_problem* p) { return ::ham_params(p); }
+uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter) { return ::make_tag(pid, step, iter); }
+}  // namespace detail
+}  // namespace hjg
 
 extern "C" {
 

@@ -143,6 +143,52 @@ hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c
 hipError_t launch_finite_check(const float* a, int64_t count, int* flag, hipStream_t s);
 hipError_t launch_fill_ints(int* a, int64_t count, int value, hipStream_t s);
 
+// Time-marching step with the surrogate network as the datum.  Rows of one
+// query chunk are r = (q - q0) N + i for q in [q0, q0 + Qc), i < N.
+// Points: X0[r][c] = bf16 of the normalised network input at
+//   y = x_q + theta_q + sigma z_i (c < n), the previous time (c = n), 0 (c < ld).
+struct TubePointsArgs {
+  int n;
+  int64_t Q, q0, Qc;
+  int N;
+  const float* x;       // [n][Q]
+  const float* theta;   // [n][Q] or nullptr
+  float sigma;
+  const void* table;    // common table [n][tstride], float32 or bf16 bits
+  int64_t tstride;
+  int bf16;
+  float t_prev;
+  const float* mean;    // input normalisation [n + 1]
+  const float* stdv;
+  int ld;               // padded input width
+  __bf16* X0;           // [Qc N][ld]
+  const int* done;      // Picard stop flag
+};
+// Log-sum-exp of one query per block over its N rows: the datum of row r is
+// Y[r][0] * ostd + omean (the network's value output), and the partials
+// (split 0) take the same form as those of the pair loops.
+struct TubeLseArgs {
+  int n;
+  int64_t Q, q0, Qc;
+  int N;
+  const float* c;       // [Q]
+  const float* theta;   // [n][Q] or nullptr
+  float sigma;
+  const void* table;
+  int64_t tstride;
+  int bf16;
+  const float* Y;       // [Qc N][ldy]
+  int ldy;
+  const float* omean;   // value output de-normalisation (device scalars)
+  const float* ostd;
+  Partials part;
+  const int* done;
+};
+constexpr int kTubeMaxSamples = 1 << 21;
+constexpr int64_t kTubeRowsPerChunk = int64_t(1) << 21;   // network rows per forward pass
+hipError_t launch_tube_points(const TubePointsArgs& a, hipStream_t s);
+hipError_t launch_tube_lse(const TubeLseArgs& a, hipStream_t s);
+
 // Item index a block of a persistent batched launch serves next: taken from
 // the work queue by one thread and shared through LDS; count or more = done.
 __device__ __forceinline__ int next_item(int* counter, int* slot) {

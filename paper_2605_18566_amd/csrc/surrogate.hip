@@ -12,12 +12,11 @@
 #include <vector>
 
 #include "hjg.h"
+#include "internal.h"
+#include "kernels.h"
 #include "mlp.h"
 
 using namespace hjg;
-
-// Defined in api.hip: per-thread error message.
-extern "C" __attribute__((visibility("hidden"))) int hjg_internal_fail(int code, const char* msg);
 
 namespace {
 
@@ -84,6 +83,8 @@ struct hjg_surrogate {
   Buf dZ[2], dZT[2];
   // training set and sweep workspace
   Buf Xall, Tall, sv, sg, tq, flags, bcount, total, index, xfb, vfb, gfb;
+  // time-marching step workspace
+  Buf mt_table, mt_zbar, mt_c, mt_th, mt_vprev, mt_pm, mt_pS, mt_pS2, mt_pG, mt_block, mt_resid, mt_ctrl;
 };
 
 namespace {
@@ -601,6 +602,173 @@ int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, in
     SG_HIP(launch_scatter_soa((const float*)s->vfb.p, 1, count, (const int*)s->index.p, Q, v, st));
     SG_HIP(launch_scatter_soa((const float*)s->gfb.p, n, count, (const int*)s->index.p, Q, grad, st));
   }
+  return HJG_OK;
+}
+
+// One time-marching step: Algorithm 1 over the horizon dt whose datum is the
+// surrogate's value at the previous time (rows of a query chunk go through
+// the network in one forward pass; the Picard bookkeeping is the sweep's).
+int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, int64_t Q, const float* x,
+                            double t_prev, double dt, int32_t N, int32_t K, double tol, uint32_t time_step,
+                            float* v, float* grad, float* c_out, float* ess, double* resid_hist,
+                            int32_t* iters_done, void* hip_stream) {
+  if (!ctx || !s) return fail(HJG_EINVAL, "context or surrogate is NULL");
+  int rc = detail::check_problem(p);
+  if (rc) return rc;
+  if (p->n != s->n) return fail(HJG_EINVAL, "problem dimension differs from the surrogate's");
+  if (p->sample_mode != HJG_S_CRN_STEP)
+    return fail(HJG_EUNSUPPORTED, "the time-marching step draws from a common table (sample_mode = crn_step)");
+  if (Q < 0 || Q > ((int64_t)1 << 30)) return fail(HJG_EINVAL, "Q must be in [0, 2^30]");
+  if (!(std::isfinite(t_prev) && t_prev >= 0)) return fail(HJG_EINVAL, "t_prev must be finite and >= 0");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(HJG_EINVAL, "dt must be finite and > 0");
+  if (N < 1 || N > kTubeMaxSamples) return fail(HJG_EINVAL, "N must be in [1, 2^21]");
+  if (K < 1 || K > 255) return fail(HJG_EINVAL, "K must be in [1, 255]");
+  if (time_step >= 256) return fail(HJG_EINVAL, "time_step must be < 256");
+  if (!(std::isfinite(tol) && tol >= 0)) return fail(HJG_EINVAL, "tol must be finite and >= 0");
+  if (iters_done) *iters_done = 0;
+  if (Q == 0) return HJG_OK;
+  if (!x || !v || !grad) return fail(HJG_EINVAL, "x, v and grad are required");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int n = s->n;
+  const bool bf16 = p->sample_bf16 != 0;
+  const int64_t tstride = (N + 63) / 64 * 64;
+  const int64_t nblocks = (Q + kThreads - 1) / kThreads;
+  int64_t rows_max = kTubeRowsPerChunk;
+  if (const char* e = std::getenv("HJG_TUBE_ROWS")) rows_max = std::max<int64_t>(1, std::atoll(e));
+  const int64_t Qc = std::max<int64_t>(1, std::min<int64_t>(Q, rows_max / N));
+  if ((rc = grow(s->mt_table, (size_t)n * tstride * (bf16 ? 2 : 4))) || (rc = grow(s->mt_zbar, kMaxN * 8)) ||
+      (rc = grow(s->mt_c, Q * 4)) || (rc = grow(s->mt_th, (size_t)Q * n * 4)) || (rc = grow(s->mt_vprev, Q * 4)) ||
+      (rc = grow(s->mt_pm, Q * 4)) || (rc = grow(s->mt_pS, Q * 8)) || (rc = grow(s->mt_pS2, Q * 8)) ||
+      (rc = grow(s->mt_pG, (size_t)Q * n * 4)) || (rc = grow(s->mt_block, nblocks * 16)) ||
+      (rc = grow(s->mt_resid, (size_t)K * 8)) || (rc = grow(s->mt_ctrl, 64)) || (rc = grow(s->tq, Q * 4)) ||
+      (rc = ensure_batch(s, Qc * N, false)))
+    return rc;
+  // the common table of (problem, time step) and its column mean
+  const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
+  SG_HIP(launch_table(n, tstride, tstride, k0, k1, detail::make_tag(p->problem_id, time_step, 0), bf16,
+                      s->mt_table.p, st));
+  if (p->grad_cv) SG_HIP(launch_zbar(n, N, tstride, bf16, s->mt_table.p, (double*)s->mt_zbar.p, st));
+  // warm start: the surrogate's value and gradient at (x, t_prev)
+  SG_HIP(launch_fill((float*)s->tq.p, (float)t_prev, Q, st));
+  if ((rc = hjg_surrogate_predict(s, Q, x, (const float*)s->tq.p, (float*)s->mt_vprev.p, grad, st))) return rc;
+
+  const float sigma = (float)std::sqrt(2.0 * p->nu * dt);
+  int* done = (int*)s->mt_ctrl.p;
+  int* iters = done + 1;
+  float* th = p->tilt ? (float*)s->mt_th.p : nullptr;
+  hjg_problem pi = *p;              // the terminal datum is not used: a harmless one for init
+  pi.datum = HJG_L_HALF_SQNORM;
+  pi.datum_aux = nullptr;
+  InitArgs in{};
+  in.n = n;
+  in.Q = Q;
+  in.K = K;
+  in.sigma = sigma;
+  in.x = x;
+  in.p0 = grad;
+  in.v0 = (const float*)s->mt_vprev.p;
+  in.dp = detail::datum_params(&pi);
+  in.hp = detail::ham_params(p);
+  in.tilt = p->tilt;
+  in.vprev = (float*)s->mt_vprev.p;
+  in.p = grad;
+  in.c = (float*)s->mt_c.p;
+  in.th = th;
+  in.done = done;
+  in.iters = iters;
+  in.resid = (double*)s->mt_resid.p;
+  SG_HIP(launch_init(in, st));
+  const Partials part{(float*)s->mt_pm.p, (double*)s->mt_pS.p, (double*)s->mt_pS2.p, (float*)s->mt_pG.p, nullptr};
+  for (int it = 0; it < K; ++it) {
+    for (int64_t q0 = 0; q0 < Q; q0 += Qc) {
+      const int64_t qc = std::min<int64_t>(Qc, Q - q0);
+      TubePointsArgs a{};
+      a.n = n;
+      a.Q = Q;
+      a.q0 = q0;
+      a.Qc = qc;
+      a.N = N;
+      a.x = x;
+      a.theta = th;
+      a.sigma = sigma;
+      a.table = s->mt_table.p;
+      a.tstride = tstride;
+      a.bf16 = bf16;
+      a.t_prev = (float)t_prev;
+      a.mean = nrm(s, 0);
+      a.stdv = nrm(s, 1);
+      a.ld = s->in_p;
+      a.X0 = (__bf16*)s->X0.p;
+      a.done = done;
+      SG_HIP(launch_tube_points(a, st));
+      if ((rc = forward(s, qc * N, false, st))) return rc;
+      TubeLseArgs l{};
+      l.n = n;
+      l.Q = Q;
+      l.q0 = q0;
+      l.Qc = qc;
+      l.N = N;
+      l.c = (const float*)s->mt_c.p;
+      l.theta = th;
+      l.sigma = sigma;
+      l.table = s->mt_table.p;
+      l.tstride = tstride;
+      l.bf16 = bf16;
+      l.Y = (const float*)s->Y.p;
+      l.ldy = s->out_p;
+      l.omean = nrm(s, 2);
+      l.ostd = nrm(s, 3);
+      l.part = part;
+      l.done = done;
+      SG_HIP(launch_tube_lse(l, st));
+    }
+    FinalizeArgs f{};
+    f.n = n;
+    f.Q = Q;
+    f.N = N;
+    f.splits = 1;
+    f.sigma = sigma;
+    f.x = x;
+    f.c = (const float*)s->mt_c.p;
+    f.theta = th;
+    f.part = part;
+    f.cv = p->grad_cv;
+    f.fresh = 0;
+    f.zbar_tab = (const double*)s->mt_zbar.p;
+    f.v = v;
+    f.grad = grad;
+    f.ess = ess;
+    f.picard = 1;
+    f.vprev = (float*)s->mt_vprev.p;
+    f.c_out = c_out;
+    f.flags = nullptr;
+    f.tol = (float)tol;
+    f.vfloor = (float)(1e-2 * std::sqrt(2.0 * p->nu * dt) * std::sqrt((double)n));
+    f.blockpart = (double*)s->mt_block.p;
+    f.c_next = (float*)s->mt_c.p;
+    f.th_next = th;
+    f.hp = in.hp;
+    f.done = done;
+    SG_HIP(launch_finalize(f, st));
+    ReduceArgs r{};
+    r.nblocks = (int)nblocks;
+    r.blockpart = (const double*)s->mt_block.p;
+    r.k = it;
+    r.tol = (float)tol;
+    r.resid = (double*)s->mt_resid.p;
+    r.done = done;
+    r.iters = iters;
+    SG_HIP(launch_reduce(r, st));
+    int flag = 0;
+    SG_HIP(hipMemcpyAsync(&flag, done, 4, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    if (flag) break;
+  }
+  int32_t nit = 0;
+  SG_HIP(hipMemcpyAsync(&nit, iters, 4, hipMemcpyDeviceToHost, st));
+  if (resid_hist) SG_HIP(hipMemcpyAsync(resid_hist, s->mt_resid.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  if (iters_done) *iters_done = nit;
   return HJG_OK;
 }
 
