@@ -403,6 +403,89 @@ def pursuit_study(ctx, stream):
                     "in float64)"}
 
 
+def tube_study(ctx, stream):
+    """Time marching with the surrogate as the datum (semigroup form): march
+    the n = 3 Dubins tube workload and the exact quadratic case over ten
+    horizons, compare with the direct horizon sweep (and, for the quadratic
+    case, with its closed form), and time the last step at 65,536 states."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import (ProblemSpec, Surrogate, TrainConfig, picard_sweep,
+                                      surrogate_tube_step)
+    cfg = workloads.TUBE_MARCH
+    res = {}
+    for w in (workloads.C2, workloads.Q3):
+        spec = ProblemSpec(**w.problem_fields())
+        dt = w.T / w.time_steps
+        M = cfg["train_states"]
+        xtr = torch.from_numpy(np.ascontiguousarray(workloads.queries(w, Q=M, trial=7).T)).to("cuda:0")
+        xev = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to("cuda:0")
+        sur = Surrogate(ctx, w.n, cfg["width"], cfg["depth"], seed=5)
+        tc = dict(epochs=cfg["epochs"], batch=cfg["batch"], lr=cfg["lr"], lr_min=cfg["lr_min"])
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            first = picard_sweep(ctx, spec, xtr, dt, cfg["N"], cfg["K"], time_step=1, host_outputs=False,
+                                 stream=stream)
+            lx, lt, lv, lg = [xtr], [torch.full((M,), dt, device="cuda:0")], [first.v.clone()], [first.grad.clone()]
+            train_s = step_s = 0.0
+            for j in range(2, w.time_steps + 1):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                sur.train(torch.cat(lx, 1).contiguous(), torch.cat(lt).contiguous(), torch.cat(lv).contiguous(),
+                          torch.cat(lg, 1).contiguous(), TrainConfig(seed=j, **tc), stream=stream)
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                o = surrogate_tube_step(ctx, sur, spec, xtr, (j - 1) * dt, dt, cfg["N"], cfg["K"], time_step=j,
+                                        stream=stream)
+                torch.cuda.synchronize()
+                train_s += b - a
+                step_s += time.perf_counter() - b
+                lx.append(xtr)
+                lt.append(torch.full((M,), j * dt, device="cuda:0"))
+                lv.append(o.v.clone())
+                lg.append(o.grad.clone())
+            march_s = time.perf_counter() - t0
+            # the last step at the evaluation states, timed warm
+            args = (ctx, sur, spec, xev, w.T - dt, dt, cfg["N"], cfg["K"])
+            surrogate_tube_step(*args, time_step=w.time_steps, stream=stream)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            ev = surrogate_tube_step(*args, time_step=w.time_steps, stream=stream)
+            torch.cuda.synchronize()
+            ev_s = time.perf_counter() - a
+            direct = picard_sweep(ctx, spec, xev, w.T, w.N, w.K, time_step=w.time_steps, host_outputs=False,
+                                  stream=stream)
+            torch.cuda.synchronize()
+        vm, vd = ev.v.cpu().numpy(), direct.v.cpu().numpy()
+        rows = w.Q * cfg["N"] * ev.iters_done
+        nin, wd, dp = w.n + 1, cfg["width"], cfg["depth"]
+        macs = nin * wd + (dp - 1) * wd * wd + wd * nin
+        r = {"states": w.Q, "samples": cfg["N"], "picard_iterations": ev.iters_done, "dt": dt,
+             "last_step_seconds": ev_s, "network_rows_per_s": rows / ev_s,
+             "network_tflops": 2.0 * macs * rows / ev_s / 1e12,
+             "mfma_frac": 2.0 * macs * rows / ev_s / 2.5e15,
+             "march_seconds": march_s, "training_seconds": train_s, "label_step_seconds": step_s,
+             "marched_vs_direct_rms": float(np.sqrt(np.mean((vm - vd) ** 2))),
+             "direct_rms": float(np.sqrt(np.mean(vd ** 2))),
+             "sign_agreement": float(np.mean(np.sign(vm) == np.sign(vd))),
+             "inside_fraction_marched": float(np.mean(vm <= 0)), "inside_fraction_direct": float(np.mean(vd <= 0))}
+        if w.ham == "quadratic":
+            x = xev.cpu().numpy().astype(np.float64)
+            exact = np.sum(x * x, 0) / (2 * (1 + w.T)) + w.n * w.nu * np.log1p(w.T)
+            r["marched_vs_exact_rms"] = float(np.sqrt(np.mean((vm - exact) ** 2)))
+            r["direct_vs_exact_rms"] = float(np.sqrt(np.mean((vd - exact) ** 2)))
+            r["exact_rms"] = float(np.sqrt(np.mean(exact ** 2)))
+        res[w.name] = r
+        sur.close()
+    return {"workload": f"ten horizons t_j = 0.1 j; labels on {cfg['train_states']} training states per step "
+                        f"(N = {cfg['N']}, K = {cfg['K']}); network {cfg['depth']} x {cfg['width']} SiLU trained "
+                        f"{cfg['epochs']} epochs per step on all labels so far; last step at the workload's states; "
+                        "direct = Algorithm 1 at the final horizon from the terminal datum",
+            "runs": res}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -441,6 +524,7 @@ def main():
     ap.add_argument("--no-flock", action="store_true", help="skip the flock study")
     ap.add_argument("--no-pursuit", action="store_true", help="skip the 45-dimensional pursuit-game study")
     ap.add_argument("--no-small", action="store_true", help="skip the C1/C2 small-configuration study")
+    ap.add_argument("--no-tube", action="store_true", help="skip the time-marching study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -525,6 +609,9 @@ def main():
     sstudy = None
     if not args.no_small:
         sstudy = small_configs_study(ctx, stream)
+    tstudy = None
+    if not args.no_tube:
+        tstudy = tube_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -568,6 +655,7 @@ def main():
         "flock": fstudy,
         "pursuit_game": pstudy,
         "small_configs": sstudy,
+        "time_marching": tstudy,
     }
     print(json.dumps(line))
 

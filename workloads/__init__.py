@@ -183,3 +183,15 @@ def c3_fields(bp: BatchProblem) -> dict:
     f = bp.w.problem_fields()
     f["seed"] = philox_seed(3) + 1000 * bp.problem_id
     return f
+
+
+# Time marching with the surrogate as the datum (semigroup form): the n = 3
+# Dubins tube workload marched over its ten horizons, and the exact Cole-Hopf
+# case H = |p|^2/2, l = |x|^2/2 (closed form at every time) marched the same
+# way.  Labels on 16,384 training states per step (N = 4,096, K = 3); a
+# 3 x 128 SiLU network trained 30 epochs per step on all labels so far; the
+# last step evaluated at the workload's 65,536 states.
+TUBE_MARCH = dict(train_states=16384, N=4096, K=3, width=128, depth=3, epochs=30, batch=1024, lr=2e-3,
+                  lr_min=1e-4)
+Q3 = Workload("q3_quadratic_n3", n=3, ham="quadratic", datum="half_sqnorm", nu=0.05, t=1.0, Q=65536, N=65536,
+              K=1, box=((-2.0, 2.0),) * 3, tilt=True, sample_mode="crn_step", cfg=8, time_steps=10, T=1.0)
