@@ -184,6 +184,36 @@ struct TubeLseArgs {
   Partials part;
   const int* done;
 };
+// Fused form for small networks (hidden width 128, padded input width 32,
+// up to three hidden layers, n <= 8): one block per query runs the inputs,
+// every layer and the value output on the matrix cores with activations in
+// LDS, and folds the values into the partials; no rows touch memory.
+constexpr int kTubeMaxDepth = 4;
+constexpr int kTubeFusedMaxDepth = 3, kTubeFusedMaxN = 8, kTubeFusedWidth = 128, kTubeFusedInP = 32;
+struct TubeFusedArgs {
+  int n;
+  int64_t Q;
+  int N;
+  int depth;
+  const float* x;       // [n][Q]
+  const float* theta;   // [n][Q] or nullptr
+  float sigma;
+  const void* table;
+  int64_t tstride;
+  int bf16;
+  float t_prev;
+  const float* mean;    // input normalisation [n + 1]
+  const float* stdv;
+  const __bf16* W[kTubeMaxDepth + 1];   // [fout][fin] bfloat16: 128 x 32, 128 x 128 ..., out_p x 128
+  const float* b[kTubeMaxDepth + 1];
+  const float* omean;
+  const float* ostd;
+  const float* c;
+  Partials part;
+  const int* done;
+};
+hipError_t launch_tube_fused(const TubeFusedArgs& a, hipStream_t s);
+
 constexpr int kTubeMaxSamples = 1 << 21;
 constexpr int64_t kTubeRowsPerChunk = int64_t(1) << 21;   // network rows per forward pass
 hipError_t launch_tube_points(const TubePointsArgs& a, hipStream_t s);

@@ -17,7 +17,8 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 constexpr int kTM = 64, kTN = 64, kTK = 32;   // block tile
 constexpr int kLdsK = kTK + 8;                 // padded LDS row (80 bytes, 16-byte aligned)
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware reciprocal (shared by every network kernel)
+__device__ __forceinline__ float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // Block tile 64 x 64, 4 waves as 2 x 2 sub-tiles of 32 x 32, each sub-tile one
 // v_mfma_f32_32x32x16_bf16 chain (two per 32-deep K slice).  Operand lanes:

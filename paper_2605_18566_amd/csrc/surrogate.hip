@@ -636,12 +636,16 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
   int64_t rows_max = kTubeRowsPerChunk;
   if (const char* e = std::getenv("HJG_TUBE_ROWS")) rows_max = std::max<int64_t>(1, std::atoll(e));
   const int64_t Qc = std::max<int64_t>(1, std::min<int64_t>(Q, rows_max / N));
+  // small networks run fused (HJG_TUBE_FUSED=0 forces the row-by-row form, for comparison)
+  const char* fe = std::getenv("HJG_TUBE_FUSED");
+  const bool fused = !(fe && fe[0] == '0') && s->width == kTubeFusedWidth && s->in_p == kTubeFusedInP &&
+                     s->depth <= kTubeFusedMaxDepth && n <= kTubeFusedMaxN;
   if ((rc = grow(s->mt_table, (size_t)n * tstride * (bf16 ? 2 : 4))) || (rc = grow(s->mt_zbar, kMaxN * 8)) ||
       (rc = grow(s->mt_c, Q * 4)) || (rc = grow(s->mt_th, (size_t)Q * n * 4)) || (rc = grow(s->mt_vprev, Q * 4)) ||
       (rc = grow(s->mt_pm, Q * 4)) || (rc = grow(s->mt_pS, Q * 8)) || (rc = grow(s->mt_pS2, Q * 8)) ||
       (rc = grow(s->mt_pG, (size_t)Q * n * 4)) || (rc = grow(s->mt_block, nblocks * 16)) ||
       (rc = grow(s->mt_resid, (size_t)K * 8)) || (rc = grow(s->mt_ctrl, 64)) || (rc = grow(s->tq, Q * 4)) ||
-      (rc = ensure_batch(s, Qc * N, false)))
+      (!fused && (rc = ensure_batch(s, Qc * N, false))))
     return rc;
   // the common table of (problem, time step) and its column mean
   const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
@@ -679,8 +683,34 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
   in.resid = (double*)s->mt_resid.p;
   SG_HIP(launch_init(in, st));
   const Partials part{(float*)s->mt_pm.p, (double*)s->mt_pS.p, (double*)s->mt_pS2.p, (float*)s->mt_pG.p, nullptr};
+  TubeFusedArgs fa{};
+  if (fused) {
+    fa.n = n;
+    fa.Q = Q;
+    fa.N = N;
+    fa.depth = s->depth;
+    fa.x = x;
+    fa.theta = th;
+    fa.sigma = sigma;
+    fa.table = s->mt_table.p;
+    fa.tstride = tstride;
+    fa.bf16 = bf16;
+    fa.t_prev = (float)t_prev;
+    fa.mean = nrm(s, 0);
+    fa.stdv = nrm(s, 1);
+    for (int l = 0; l <= s->depth; ++l) {
+      fa.W[l] = (const __bf16*)s->Wb[l].p;
+      fa.b[l] = (const float*)s->w.p + s->boff[l];
+    }
+    fa.omean = nrm(s, 2);
+    fa.ostd = nrm(s, 3);
+    fa.c = (const float*)s->mt_c.p;
+    fa.part = part;
+    fa.done = done;
+  }
   for (int it = 0; it < K; ++it) {
-    for (int64_t q0 = 0; q0 < Q; q0 += Qc) {
+    if (fused) SG_HIP(launch_tube_fused(fa, st));
+    for (int64_t q0 = 0; q0 < Q && !fused; q0 += Qc) {
       const int64_t qc = std::min<int64_t>(Qc, Q - q0);
       TubePointsArgs a{};
       a.n = n;
