@@ -31,6 +31,10 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   mlp.forward_bf16_storage /     : reduces to the plain forward when rounding
     value_at, round_bf16           is the identity; rounding ties by hand and
                                    against the draw generator's rounding
+  certify.classify / mc_margin / : the corollary's sign guarantee as a property;
+    error_budget                   the margin inverts the tail bound, has
+                                   Hoeffding's c -> 0 limit and covers the
+                                   exact quadratic case over 200 draw sets
   model.hamiltonian (Dubins,     : brute-force max-min over control grids
     multi-pursuer game)
   model.coefficient              : direct evaluation checks (sign, clip, eta)
