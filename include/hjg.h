@@ -400,6 +400,57 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
                             double* resid_hist, int32_t* iters_done, void* hip_stream);
 
 /*
+ * ------------------------------------------------------------------------
+ * Conservative safety certification (corollary "conservative safety
+ * certification" of the total-error theorem).  A state is unsafe iff its
+ * value is <= 0.  With a total error budget E the estimate certifies a state
+ * SAFE only if v > E and UNSAFE only if v < -E; everything else is
+ * UNDETERMINED, so with the theorem's probability no unsafe state is called
+ * safe and no safe state unsafe.
+ * ------------------------------------------------------------------------
+ */
+typedef struct hjg_budget {
+  double C1, rho;      /* iteration term C1 rho^K                                 */
+  int32_t K;
+  double C2;           /* sampling term C2 sqrt(log(1/delta_p) / N)               */
+  int64_t N;
+  double delta_p;      /* failure probability, in (0, 1)                          */
+  double eps_ql;       /* quasi-linearisation defect                              */
+  double C3, delta;    /* viscosity term C3 sqrt(delta)                           */
+} hjg_budget;
+/* E = C1 rho^K + C2 sqrt(log(1/delta_p)/N) + eps_ql + C3 sqrt(delta) (host
+ * arithmetic; the constants are the caller's).  HJG_EINVAL on NULL or on
+ * negative terms. */
+int hjg_error_budget(const hjg_budget* b, double* E);
+/* Per-state sampling margin of the finite-sample concentration theorem for
+ * the plain (unshifted) estimator with frozen coefficient c: Z = exp(-c g)
+ * lies in [alpha, beta], the smaller and larger of exp(-c g_min) and
+ * exp(-c g_max) (remark on the sign of the coefficient; g_max may be
+ * +infinity), and with the mean taken as mu = exp(-c v) (the estimate's own)
+ *   margin = -log(1 - r)/|c|,  r = (beta - alpha)/mu sqrt(log(2/delta_p)/(2N)),
+ * or +infinity where r >= 1 (no finite margin at this N).  As c -> 0 it
+ * tends to Hoeffding's (g_max - g_min) sqrt(log(2/delta_p)/(2N)).  With ess
+ * (device [Q], the sweep's effective sample sizes) the variance-aware
+ * empirical Bernstein form replaces it (the tighter kind of bound the paper's
+ * remark on Bernstein points to; Maurer and Pontil 2009, two-sided):
+ *   r = sqrt(2 V L/N) + 7 (beta - alpha)/mu L/(3(N - 1)),  L = log(4/delta_p),
+ *   V = N/(N-1) (N/ESS - 1) (relative sample variance of the weights).
+ * v, c device [Q]; margin device [Q] out (float32, computed in float64).
+ * Asynchronous.  HJG_EINVAL: N < 1 (N < 2 with ess), delta_p outside (0, 1),
+ * g_min not finite or g_max < g_min. */
+int hjg_mc_margin(int64_t Q, const float* v, const float* c, const float* ess,
+                  int32_t N, double delta_p, double g_min, double g_max,
+                  float* margin, void* hip_stream);
+/* Labels: label[q] = +1 (SAFE) if v[q] > E + m[q], -1 (UNSAFE) if
+ * v[q] < -(E + m[q]), 0 (UNDETERMINED) otherwise, compared in float64, with
+ * m = margin (device [Q]) or 0 when margin is NULL; label device int8 [Q] out
+ * or NULL; counts device int64 [3] out or NULL: the number of UNSAFE,
+ * UNDETERMINED and SAFE states (population certification).  Asynchronous.
+ * HJG_EINVAL: E negative or not finite, both outputs NULL. */
+int hjg_certify(int64_t Q, const float* v, const float* margin, double E,
+                int8_t* label, int64_t* counts, void* hip_stream);
+
+/*
  * Kernel timing (profiling hook).  With timing enabled, every launch of the
  * pair-loop kernel made by hjg_value_grad / hjg_picard_sweep is bracketed by
  * HIP events on the caller's stream; while timing is on, the Picard loop is

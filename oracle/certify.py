@@ -15,7 +15,15 @@ Written from the paper:
   so at confidence delta_p: r = (beta - alpha) / mu * sqrt(log(2/delta_p) / (2N)),
   eps = -log(1 - r) / |c| when r < 1, else no finite margin.  The mean mu is
   taken as exp(-c v_hat) (the estimate itself; the paper allows a sharper
-  estimate of mu in place of its lower bound alpha), or passed in.
+  estimate of mu in place of its lower bound alpha), or passed in;
+* the variance-aware margin the paper's remark on Bernstein bounds points to,
+  from the empirical Bernstein inequality (Maurer and Pontil, 2009, Thm. 4,
+  two-sided: confidence split between the two tails): with the sample mean
+  Zbar, the unbiased sample variance V and the range R = beta - alpha,
+      |Zbar - mu| <= sqrt(2 V log(4/delta_p) / N) + 7 R log(4/delta_p) / (3 (N - 1)),
+  and V / Zbar^2 = N/(N-1) (N / ESS - 1) in terms of the effective sample
+  size ESS = S^2 / S2 of the sweep; with rho = |Zbar - mu| / Zbar < 1 the
+  value error is at most -log(1 - rho) / |c|.
 """
 from __future__ import annotations
 
@@ -48,4 +56,20 @@ def mc_margin(v, c, N, delta_p, g_min, g_max=np.inf, mu=None):
         mu = np.exp(-c * v) if mu is None else np.asarray(mu, dtype=np.float64)
         r = (beta - alpha) / mu * np.sqrt(np.log(2.0 / delta_p) / (2.0 * N))
         eps = np.where(r < 1.0, -np.log1p(-np.minimum(r, 1.0)) / np.abs(c), np.inf)
+    return eps
+
+
+def bernstein_margin(v, c, ess, N, delta_p, g_min, g_max=np.inf):
+    """Per-state margin from the empirical Bernstein inequality (inf where none)."""
+    v = np.asarray(v, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    ess = np.asarray(ess, dtype=np.float64)
+    L = np.log(4.0 / delta_p)
+    with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+        e1, e2 = np.exp(-c * g_min), np.exp(-c * g_max)
+        R = np.maximum(e1, e2) - np.minimum(e1, e2)
+        zbar = np.exp(-c * v)
+        var_rel = N / (N - 1.0) * np.maximum(N / ess - 1.0, 0.0)
+        rho = np.sqrt(2.0 * var_rel * L / N) + 7.0 * (R / zbar) * L / (3.0 * (N - 1.0))
+        eps = np.where(rho < 1.0, -np.log1p(-np.minimum(rho, 1.0)) / np.abs(c), np.inf)
     return eps

@@ -56,6 +56,20 @@ class TrainCfg(C.Structure):
     ]
 
 
+class Budget(C.Structure):
+    _fields_ = [
+        ("C1", C.c_double),
+        ("rho", C.c_double),
+        ("K", C.c_int32),
+        ("C2", C.c_double),
+        ("N", C.c_int64),
+        ("delta_p", C.c_double),
+        ("eps_ql", C.c_double),
+        ("C3", C.c_double),
+        ("delta", C.c_double),
+    ]
+
+
 class HJGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"hjg error {code}: {msg}")
@@ -112,6 +126,10 @@ SIGNATURES = [
                                           C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_uint32,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                           C.POINTER(C.c_int32), C.c_void_p]),
+    ("hjg_error_budget", C.c_int, [C.POINTER(Budget), C.POINTER(C.c_double)]),
+    ("hjg_mc_margin", C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_void_p, C.c_void_p]),
+    ("hjg_certify", C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hjg_set_timing", C.c_int, [C.c_void_p, C.c_int32]),
     ("hjg_sweep_time", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("hjg_picard_sweep", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,

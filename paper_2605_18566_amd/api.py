@@ -454,3 +454,39 @@ def surrogate_tube_step(ctx: Context, sur: Surrogate, spec: ProblemSpec, x: torc
     out.resid_hist = np.array(list(hist))
     out.iters_done = int(iters.value)
     return out
+
+
+# ------------------------------------------------------------- certification
+def error_budget(C1: float, rho: float, K: int, C2: float, N: int, delta_p: float, eps_ql: float = 0.0,
+                 C3: float = 0.0, delta: float = 0.0) -> float:
+    """E = C1 rho^K + C2 sqrt(log(1/delta_p)/N) + eps_ql + C3 sqrt(delta) (hjg_error_budget)."""
+    b = _lib.Budget(C1=C1, rho=rho, K=K, C2=C2, N=N, delta_p=delta_p, eps_ql=eps_ql, C3=C3, delta=delta)
+    E = C.c_double(0.0)
+    check(_lib.lib().hjg_error_budget(C.byref(b), C.byref(E)))
+    return float(E.value)
+
+
+def mc_margin(v: torch.Tensor, c: torch.Tensor, N: int, delta_p: float, g_min: float, g_max: float = float("inf"),
+              ess: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Per-state sampling margin: the concentration theorem (Hoeffding), or with
+    ess the empirical Bernstein form (hjg_mc_margin)."""
+    _require_cuda(v, "v")
+    _require_cuda(c, "c")
+    if ess is not None:
+        _require_cuda(ess, "ess")
+    out = torch.empty_like(v)
+    check(_lib.lib().hjg_mc_margin(v.numel(), _ptr(v), _ptr(c), _ptr(ess), int(N), float(delta_p), float(g_min),
+                                   float(g_max), _ptr(out), _stream(stream)))
+    return out
+
+
+def certify(v: torch.Tensor, E: float = 0.0, margin: Optional[torch.Tensor] = None, stream=None):
+    """Labels (+1 SAFE, -1 UNSAFE, 0 UNDETERMINED) and the counts (unsafe, undetermined, safe)."""
+    _require_cuda(v, "v")
+    if margin is not None:
+        _require_cuda(margin, "margin")
+    label = torch.empty(v.numel(), dtype=torch.int8, device=v.device)
+    counts = torch.empty(3, dtype=torch.int64, device=v.device)
+    check(_lib.lib().hjg_certify(v.numel(), _ptr(v), _ptr(margin), float(E), _ptr(label), _ptr(counts),
+                                 _stream(stream)))
+    return label, counts

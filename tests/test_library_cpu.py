@@ -53,6 +53,24 @@ def test_struct_layout_matches_header(lib, tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(_lib.Problem), _lib.Problem.datum_aux.offset, _lib.Problem.seed.offset,
                    _lib.Problem.problem_id.offset]
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hjg.h"\nint main(){printf("%zu %zu %zu %zu\\n",'
+                   'sizeof(hjg_budget), offsetof(hjg_budget, C2), offsetof(hjg_budget, N),'
+                   'offsetof(hjg_budget, delta));return 0;}\n')
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(_lib.Budget), _lib.Budget.C2.offset, _lib.Budget.N.offset, _lib.Budget.delta.offset]
+
+
+def test_error_budget_matches_oracle(lib):
+    # host arithmetic only: no device needed
+    import numpy as np
+    from oracle import certify as oc
+    from paper_2605_18566_amd import error_budget
+    args = (1.5, 0.7, 5, 2.0, 65536, 0.01, 3e-3, 0.8, 0.02)
+    np.testing.assert_allclose(error_budget(*args), oc.error_budget(*args), rtol=1e-15)
+    from paper_2605_18566_amd import _lib
+    with pytest.raises(_lib.HJGError):
+        error_budget(1.0, 0.5, 3, 1.0, 100, 1.5)
 
 
 def test_version_and_error_paths_without_device(lib):

@@ -75,3 +75,31 @@ def test_margin_covers_the_exact_case():
     assert np.all(np.isfinite(eps_true))
     assert miss_true <= dp * 3 * trials and miss_hat <= dp * 3 * trials
     assert miss_true == 0                       # the bound is far from tight here
+
+
+def test_bernstein_margin_covers_the_exact_case_and_is_tighter():
+    # the same exact case; the empirical Bernstein margin needs the sweep's
+    # ESS; it must cover the error at least as often as promised, and it is
+    # far narrower than Hoeffding's where the weight range is wide
+    nu, t, N, dp = 0.05, 0.5, 2048, 0.1
+    pb = model.Problem(n=1, ham="quadratic", datum="half_sqnorm", nu=nu, sample_mode="fresh")
+    x = np.array([[0.0], [0.3], [0.6], [1.1]])
+    c = np.full(4, 1.0 / pb.delta)
+    v_exact = x[:, 0] ** 2 / (2 * (1 + t)) + nu * np.log1p(t)
+    miss = 0
+    trials = 200
+    widths_b, widths_h = [], []
+    for s in range(trials):
+        est = estimator.value_grad(model.Problem(**{**pb.__dict__, "seed": 5000 + s}), x, t, N, c)
+        eb = certify.bernstein_margin(est.v, c, est.ess, N, dp, 0.0)
+        miss += np.sum(np.abs(est.v - v_exact) >= eb)
+        widths_b.append(eb)
+        widths_h.append(certify.mc_margin(est.v, c, N, dp, 0.0))
+    assert miss <= dp * 3 * trials
+    wb, wh = np.median(widths_b, 0), np.median(widths_h, 0)
+    assert np.all(wb < wh)
+    # at x = 1.1 the weight range over the mean is ~60: no Hoeffding margin at
+    # this N, a finite Bernstein one
+    assert np.isinf(wh[3]) and np.isfinite(wb[3])
+    # zero variance (ESS = N) and a zero range give a zero margin
+    np.testing.assert_array_equal(certify.bernstein_margin([0.2], [1.0], [N], N, dp, 0.5, 0.5), [0.0])
