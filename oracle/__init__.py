@@ -35,6 +35,9 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
     error_budget                   the margin inverts the tail bound, has
                                    Hoeffding's c -> 0 limit and covers the
                                    exact quadratic case over 200 draw sets
+  topology.markers / events      : hand-built slices of plain topology (discs,
+                                   rings, holes open to the border, diagonal
+                                   contact) and a hand-made event sequence
   model.hamiltonian (Dubins,     : brute-force max-min over control grids
     multi-pursuer game)
   model.coefficient              : direct evaluation checks (sign, clip, eta)
