@@ -451,6 +451,28 @@ int hjg_certify(int64_t Q, const float* v, const float* margin, double E,
                 int8_t* label, int64_t* counts, void* hip_stream);
 
 /*
+ * ------------------------------------------------------------------------
+ * Topology markers of the zero-sublevel set {v <= 0} on 2D slices (appendix
+ * on vacuole nucleation topology: its detection algorithm and event rules).
+ * ------------------------------------------------------------------------
+ */
+enum { HJG_EVENT_VACUOLE = 1, HJG_EVENT_CORDON = 2, HJG_EVENT_FRAGMENTATION = 4 };
+/* For B slices of ny x nx grid values (v device float32 [B][ny][nx],
+ * row-major, ny nx <= 16,384): n_comp[b] = connected components of
+ * {v <= 0} (4-neighbour), beta1[b] = components of {v > 0} (4-neighbour)
+ * that touch no edge of the grid, chi[b] = n_comp - beta1 (device int32 [B]
+ * out).  A NaN counts as v > 0.  Asynchronous.  HJG_EINVAL on bad sizes or
+ * NULL, HJG_EUNSUPPORTED for larger slices. */
+int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v,
+                 int32_t* n_comp, int32_t* beta1, int32_t* chi, void* hip_stream);
+/* Event bits per step from the markers of T consecutive steps (host arrays):
+ * HJG_EVENT_VACUOLE where chi[t] - chi[t-1] < -0.5, HJG_EVENT_CORDON where
+ * beta1[t] >= 1 and beta1[t-1] == 0, HJG_EVENT_FRAGMENTATION where
+ * n_comp[t] > n_comp[t-1]; events[0] = 0.  Host arithmetic. */
+int hjg_topology_events(int32_t T, const int32_t* chi, const int32_t* beta1,
+                        const int32_t* n_comp, int32_t* events);
+
+/*
  * Kernel timing (profiling hook).  With timing enabled, every launch of the
  * pair-loop kernel made by hjg_value_grad / hjg_picard_sweep is bracketed by
  * HIP events on the caller's stream; while timing is on, the Picard loop is

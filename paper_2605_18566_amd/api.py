@@ -490,3 +490,25 @@ def certify(v: torch.Tensor, E: float = 0.0, margin: Optional[torch.Tensor] = No
     check(_lib.lib().hjg_certify(v.numel(), _ptr(v), _ptr(margin), float(E), _ptr(label), _ptr(counts),
                                  _stream(stream)))
     return label, counts
+
+
+# ------------------------------------------------------------------ topology
+def topology(v: torch.Tensor, stream=None):
+    """Markers of {v <= 0} on slices v [B, ny, nx] (or [ny, nx]): (n_comp, beta1, chi) int32 tensors [B]."""
+    _require_cuda(v, "v")
+    if v.dim() == 2:
+        v = v.unsqueeze(0)
+    B, ny, nx = v.shape
+    out = [torch.empty(B, dtype=torch.int32, device=v.device) for _ in range(3)]
+    check(_lib.lib().hjg_topology(B, ny, nx, _ptr(v), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(stream)))
+    return tuple(out)
+
+
+def topology_events(chi, beta1, n_comp) -> np.ndarray:
+    """Event bits per step (1 vacuole nucleation, 2 cordon formation, 4 fragmentation)."""
+    chi, beta1, n_comp = (np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (chi, beta1, n_comp))
+    T = len(chi)
+    ev = np.zeros(T, dtype=np.int32)
+    check(_lib.lib().hjg_topology_events(T, chi.ctypes.data, beta1.ctypes.data, n_comp.ctypes.data,
+                                         ev.ctypes.data))
+    return ev

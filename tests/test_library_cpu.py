@@ -105,3 +105,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         _lib.lib()
+
+
+def test_topology_events_match_oracle(lib):
+    # host arithmetic only
+    import numpy as np
+    from oracle import topology as ot
+    from paper_2605_18566_amd import topology_events
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        T = int(rng.integers(1, 30))
+        ncomp = rng.integers(0, 4, T)
+        beta1 = rng.integers(0, 3, T) * rng.integers(0, 2, T)
+        chi = ncomp - beta1
+        np.testing.assert_array_equal(topology_events(chi, beta1, ncomp), ot.events(chi, beta1, ncomp))
