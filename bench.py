@@ -520,6 +520,46 @@ def tube_study(ctx, stream):
             "runs": res}
 
 
+def topology_study(ctx, stream):
+    """Topology markers of the Dubins tube's zero-sublevel set on the slice
+    heading = 0 (128 x 128 states over [-3, 3]^2) at the ten horizons, and
+    the event rules between consecutive horizons."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, picard_sweep, topology, topology_events
+    w = workloads.C2
+    m = 128
+    g = np.linspace(-3.0, 3.0, m)
+    X, Y = np.meshgrid(g, g)
+    xs = np.stack([X.ravel(), Y.ravel(), np.zeros(m * m)]).astype(np.float32)
+    x = torch.from_numpy(xs).to("cuda:0")
+    spec = ProblemSpec(**w.problem_fields())
+    vs = []
+    with torch.cuda.stream(stream):
+        for j in range(1, w.time_steps + 1):
+            o = picard_sweep(ctx, spec, x, w.T * j / w.time_steps, w.N, w.K, time_step=j, host_outputs=False,
+                             stream=stream)
+            vs.append(o.v.view(m, m))
+        v = torch.stack(vs).contiguous()
+        topology(v, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nc, b1, chi = topology(v, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+    nc, b1, chi = nc.cpu().numpy(), b1.cpu().numpy(), chi.cpu().numpy()
+    ev = topology_events(chi, b1, nc)
+    names = {1: "vacuole", 2: "cordon", 4: "fragmentation"}
+    return {"workload": f"{w.name}: slice heading = 0, {m} x {m} states over [-3, 3]^2, horizons t_j = 0.1 j, "
+                        f"N = {w.N}, K = {w.K}",
+            "n_comp": nc.tolist(), "beta1": b1.tolist(), "chi": chi.tolist(),
+            "inside_fraction": [float((vv <= 0).float().mean()) for vv in vs],
+            "events": [[names[b] for b in (1, 2, 4) if e & b] for e in ev.tolist()],
+            "topology_ms_for_all_slices": ms}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -559,6 +599,7 @@ def main():
     ap.add_argument("--no-pursuit", action="store_true", help="skip the 45-dimensional pursuit-game study")
     ap.add_argument("--no-small", action="store_true", help="skip the C1/C2 small-configuration study")
     ap.add_argument("--no-tube", action="store_true", help="skip the time-marching study")
+    ap.add_argument("--no-topology", action="store_true", help="skip the topology-marker study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -646,6 +687,9 @@ def main():
     tstudy = None
     if not args.no_tube:
         tstudy = tube_study(ctx, stream)
+    topo = None
+    if not args.no_topology:
+        topo = topology_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -690,6 +734,7 @@ def main():
         "pursuit_game": pstudy,
         "small_configs": sstudy,
         "time_marching": tstudy,
+        "topology": topo,
     }
     print(json.dumps(line))
 
