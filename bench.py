@@ -434,7 +434,7 @@ def pursuit_study(ctx, stream):
             "regimes": rows,
             "note": "the paper does not state its state count or N for this table; 1,600 states and N = 20,000 "
                     "are readings (its 3D slices use 1,600 points; 7.2 MB per iteration at n = 45 is N = 20,000 "
-                    "in float64)"}
+                    "in float64); positions uniform over [-100, 100] per coordinate as the paper states"}
 
 
 def tube_study(ctx, stream):
@@ -560,6 +560,41 @@ def topology_study(ctx, stream):
             "topology_ms_for_all_slices": ms}
 
 
+def rockets_study(ctx, stream):
+    """The paper's two-rocket game (Table 1 rows "Rockets"): 40 x 40 (x, z)
+    slices at the headings -pi/2, 0, pi/2, N = 14,000 fresh draws, K = 12;
+    wall time per slice next to the paper's single-core times."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, picard_sweep
+    w = workloads.C7
+    spec = ProblemSpec(**w.problem_fields())
+    paper_s = {"-pi/2": 13.5, "0": 13.5, "pi/2": 13.6}
+    rows = {}
+    with torch.cuda.stream(stream):
+        for name, th in zip(("-pi/2", "0", "pi/2"), workloads.ROCKET_HEADINGS):
+            x = torch.from_numpy(np.ascontiguousarray(workloads.rocket_slice(th).T)).to("cuda:0")
+            picard_sweep(ctx, spec, x, w.t, w.N, w.K, stream=stream)          # records the graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = picard_sweep(ctx, spec, x, w.t, w.N, w.K, stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows[name] = {"seconds": dt, "query_samples_per_s": w.Q * w.N * w.K / dt,
+                          "final_relative_residual": float(out.resid_hist[-1]),
+                          "inside_fraction": float((out.v <= 0).float().mean()),
+                          "paper_seconds_one_cpu_core": paper_s[name]}
+    return {"workload": f"{w.name}: relative (x, z, theta), a = 64, g = 32, |u| <= 1, capture radius 1.5, "
+                        f"40 x 40 slices of (-100, 100]^2, N = {w.N} fresh draws, K = {w.K}, nu = {w.nu}, "
+                        "tube coefficient, plain estimator",
+            "headings": rows,
+            "note": "the Hamiltonian is derived from the rows of the paper's definition (its simplified form swaps "
+                    "u_e and u_p and drops a sign); the paper's residual floor for this game is 0.020-0.062 over "
+                    "its own evaluation grid"}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -600,6 +635,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the C1/C2 small-configuration study")
     ap.add_argument("--no-tube", action="store_true", help="skip the time-marching study")
     ap.add_argument("--no-topology", action="store_true", help="skip the topology-marker study")
+    ap.add_argument("--no-rockets", action="store_true", help="skip the two-rocket game study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -690,6 +726,9 @@ def main():
     topo = None
     if not args.no_topology:
         topo = topology_study(ctx, stream)
+    rstudy = None
+    if not args.no_rockets:
+        rstudy = rockets_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -735,6 +774,7 @@ def main():
         "small_configs": sstudy,
         "time_marching": tstudy,
         "topology": topo,
+        "rockets_game": rstudy,
     }
     print(json.dumps(line))
 

@@ -74,11 +74,18 @@ enum hjg_ham {
   HJG_H_ZERO = 2,            /* H = 0 (pure diffusion; c = +c_min)                     */
   HJG_H_DOUBLE_INTEGRATOR = 3,/* n = 6, x = (pos, vel): <p_pos, vel> + u_max |p_vel|;
                                 ham_p = {u_max}                                       */
-  HJG_H_PURSUIT_EVASION = 4  /* multi-pursuer single-evader game (Section 3.2): m = n/3
+  HJG_H_PURSUIT_EVASION = 4, /* multi-pursuer single-evader game (Section 3.2): m = n/3
                                 planar agents (x, y, heading), the last the evader;
                                 sum_j a_j (p_xj cos th_j + p_yj sin th_j)
                                 + u_max |p_th,evader| - u_max sum_pursuers |p_th,j|;
                                 ham_p = {a_evader, a_pursuer, u_max}; 2 <= m <= 16 */
+  HJG_H_ROCKETS = 5          /* two rockets on a plane (appendix, game of two rockets),
+                                n = 3, x = (x, z, theta) relative: with the rows of
+                                its Hamiltonian definition eq. (ham_general),
+                                H = -[a p1 cos th + p2 (a + a sin th - g)
+                                      + u_max |p1 x - p3| - u_max |p2 x + p3|]
+                                (evader u_e maximises, pursuer u_p minimises,
+                                |u| <= u_max); ham_p = {a, g, u_max}              */
 };
 
 /* Terminal data l(y) (signed distance: negative inside the target set). */

@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator", "pursuit_evasion")
+HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator", "pursuit_evasion", "rockets")
 DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear", "capture")
 
 
@@ -23,7 +23,7 @@ DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear", "captu
 class Problem:
     """One problem instance; mirrors the fields of the library's problem record.
 
-    ham_p:   quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
+    ham_p:   rockets: (a, g, u_max).  quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
              sign of the p2 term (+1 from the relative dynamics, -1 for the form
              the paper prints).  double_integrator: (u_max,).
              pursuit_evasion: (a_evader, a_pursuer, u_max) for m = n/3 planar
@@ -187,6 +187,16 @@ def hamiltonian(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
             H += a * (p[:, 3 * j] * np.cos(th) + p[:, 3 * j + 1] * np.sin(th))
             H += (umax if j == m - 1 else -umax) * np.abs(p[:, 3 * j + 2])
         return H
+    if kind == "rockets":
+        # Two rockets on a plane (appendix, game of two rockets), relative
+        # state (x, z, theta): with the rows of the Hamiltonian's definition,
+        # x' = a cos th + u_e x, z' = a sin th + a + u_p x - g, th' = u_p - u_e,
+        # and H = -max_{u_e} min_{u_p} <p, f> over |u| <= u_max.
+        a, g, umax = (float(v) for v in pb.ham_p[:3])
+        xx, th = x[:, 0], x[:, 2]
+        p1, p2, p3 = p[:, 0], p[:, 1], p[:, 2]
+        inner = a * p1 * np.cos(th) + p2 * (a + a * np.sin(th) - g)
+        return -(inner + umax * np.abs(p1 * xx - p3) - umax * np.abs(p2 * xx + p3))
     if kind == "double_integrator":
         # pos' = vel, vel' = u with ||u|| <= u_max, the agent maximising.
         umax = float(pb.ham_p[0])

@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "libhjg.so")
 # enum values of include/hjg.h
 HJG_OK, HJG_ENOTCONVERGED = 0, 1
 HJG_EINVAL, HJG_ENOMEM, HJG_EHIP, HJG_ENONFINITE, HJG_EUNSUPPORTED = -1, -2, -3, -4, -5
-HAMILTONIANS = {"quadratic": 0, "dubins_pairs": 1, "zero": 2, "double_integrator": 3, "pursuit_evasion": 4}
+HAMILTONIANS = {"quadratic": 0, "dubins_pairs": 1, "zero": 2, "double_integrator": 3, "pursuit_evasion": 4,
+                "rockets": 5}
 DATUMS = {"half_sqnorm": 0, "ball": 1, "min_pair_disks": 2, "knn_balls": 3, "linear": 4, "capture": 5}
 SAMPLE_MODES = {"fresh": 0, "crn_step": 1}
 

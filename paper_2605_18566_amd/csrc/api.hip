@@ -154,6 +154,12 @@ int check_problem(const hjg_problem* p) {
         if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
       if (!(p->ham_p[2] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
       break;
+    case HJG_H_ROCKETS:
+      if (p->n != 3) return fail(HJG_EINVAL, "the rockets game needs n = 3");
+      for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
+      if (!(p->ham_p[2] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
+      break;
     case HJG_H_DOUBLE_INTEGRATOR:
       if (p->n != 6) return fail(HJG_EINVAL, "the double integrator needs n = 6");
       if (!(std::isfinite(p->ham_p[0]) && p->ham_p[0] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");

@@ -221,6 +221,15 @@ __device__ inline float hamiltonian(const HamP& hp, const float* x, const float*
       const float pv = sqrtf(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
       return p[0] * x[3] + p[1] * x[4] + p[2] * x[5] + hp.p[0] * pv;
     }
+    case HJG_H_ROCKETS: {
+      // relative rockets: x' = a cos th + u_e x, z' = a sin th + a + u_p x - g,
+      // th' = u_p - u_e; H = -max_{u_e} min_{u_p} <p, f>
+      const float a = hp.p[0], g = hp.p[1], um = hp.p[2];
+      float s3, c3;
+      sincosf(x[2], &s3, &c3);
+      return -(a * p[0] * c3 + p[1] * (a + a * s3 - g) + um * fabsf(p[0] * x[0] - p[2]) -
+               um * fabsf(p[1] * x[0] + p[2]));
+    }
     case HJG_H_ZERO:
     default:
       return 0.f;

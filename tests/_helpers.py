@@ -50,3 +50,13 @@ def grad_tol(g_or, c, sigma, N):
     """Gradient tolerance: 1e-3 max(|Dv|, 1/(|c| sigma sqrt(N))) per query (2-norm)."""
     gn = np.linalg.norm(g_or, axis=-1)
     return 1e-3 * np.maximum(gn, 1.0 / (np.abs(c) * sigma * np.sqrt(N)))
+
+
+def ess_rtol(c, theta, sigma, lmax):
+    """Relative ESS tolerance: each log-weight carries |delta a| <= 64 u32 |c| L
+    (as in value_tol), which moves S by at most that fraction and S2 by twice
+    it, so ESS = S^2/S2 by at most four times: 1e-3 + 256 u32 |c| L."""
+    c = np.abs(np.asarray(c, dtype=np.float64))
+    th2 = np.sum(np.asarray(theta, dtype=np.float64) ** 2, axis=-1) if theta is not None else 0.0
+    cL = c * lmax + th2 / (2 * sigma ** 2) + np.sqrt(th2) * 6.0 / sigma
+    return 1e-3 + 256 * U32 * cL

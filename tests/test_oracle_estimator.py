@@ -307,6 +307,26 @@ def test_double_integrator_hamiltonian_brute_force():
     assert abs(model.hamiltonian(pb, x[None], p[None])[0] - brute) < 1e-3
 
 
+def test_rockets_hamiltonian_brute_force():
+    # -max over u_e of min over u_p of <p, f(x, u_e, u_p)> on control grids
+    # that contain the bang-bang corners, with the dynamics rows of the
+    # Hamiltonian's definition in the appendix on the game of two rockets
+    rng = np.random.default_rng(12)
+    a, g, um = 64.0, 32.0, 1.0
+    pb = model.Problem(n=3, ham="rockets", datum="ball", datum_p=(2, 1.5), nu=0.04, ham_p=(a, g, um))
+    us = np.linspace(-um, um, 41)
+    for _ in range(6):
+        x = np.array([rng.uniform(-100, 100), rng.uniform(-100, 100), rng.uniform(-np.pi / 2, np.pi / 2)])
+        p = rng.standard_normal(3)
+        ue, up = np.meshgrid(us, us, indexing="ij")
+        f1 = a * np.cos(x[2]) + ue * x[0]
+        f2 = a * np.sin(x[2]) + a + up * x[0] - g
+        f3 = up - ue
+        val = p[0] * f1 + p[1] * f2 + p[2] * f3
+        brute = -np.max(np.min(val, axis=1))
+        np.testing.assert_allclose(model.hamiltonian(pb, x[None], p[None])[0], brute, rtol=1e-12, atol=1e-9)
+
+
 def test_coefficient_sign_clip_and_regularisation():
     pb = model.Problem(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
                        eta=0.01, c_min=0.5, c_max=20.0)

@@ -133,8 +133,9 @@ def flock_agents(M: int = 100000, trial: int = 0, extent: Optional[float] = None
 # three speed regimes; delta = 0.08 (nu = 0.04) as in the paper's 3D games,
 # N = 20,000 draws (the 7.2 MB per iteration the paper reports at n = 45),
 # K = 15 iterations, 1,600 evaluation states (a 40 x 40 slice's count) with
-# positions in a 20 x 20 square and headings in [-pi, pi), t = 1.
-def pursuit_box(m: int, half: float = 10.0):
+# positions uniform over [-100, 100] per coordinate (the paper's statement for
+# this game) and headings in [-pi, pi), t = 1.
+def pursuit_box(m: int, half: float = 100.0):
     return tuple([(-half, half), (-half, half), (-PI, PI)] * m)
 
 
@@ -145,6 +146,25 @@ PURSUIT_REGIMES = {"evader_faster": (2.0, 1.0), "equal_speed": (1.0, 1.0), "purs
 C6 = Workload("c6_pursuit15_n45", n=45, ham="pursuit_evasion", ham_p=(2.0, 1.0, 1.0), datum="capture",
               datum_p=(1.5,), nu=0.04, t=1.0, Q=1600, N=20000, K=15, box=pursuit_box(15), tilt=False,
               sample_mode="crn_step", sample_bf16=True, cfg=7, tube=True)
+
+
+# The paper's two-rocket game (appendix, game of two rockets; Table 1):
+# relative state (x, z, theta), a = 64, g = 32 (ft/s^2), |u| <= 1, capture
+# radius 1.5 in (x, z), delta = 0.08 (nu = 0.04), t = 1, N = 14,000 draws
+# per state and iteration (fresh, as the paper resamples), K = 12 iterations,
+# tube coefficient, plain estimator; evaluation on 40 x 40 (x, z) slices of
+# (-100, 100]^2 at the headings -pi/2, 0 and pi/2.
+ROCKET_HEADINGS = (-PI / 2, 0.0, PI / 2)
+C7 = Workload("c7_rockets_n3", n=3, ham="rockets", ham_p=(64.0, 32.0, 1.0), datum="ball", datum_p=(2, 1.5),
+              nu=0.04, t=1.0, Q=1600, N=14000, K=12, box=((-100.0, 100.0), (-100.0, 100.0), (-PI / 2, PI / 2)),
+              tilt=False, sample_mode="fresh", cfg=9, tube=True)
+
+
+def rocket_slice(theta: float, m: int = 40) -> np.ndarray:
+    """States of an m x m (x, z) slice of (-100, 100]^2 at heading theta, float32 [m*m, 3]."""
+    g = -100.0 + 200.0 * (np.arange(m) + 1) / m
+    X, Z = np.meshgrid(g, g)
+    return np.stack([X.ravel(), Z.ravel(), np.full(m * m, theta)], 1).astype(np.float32)
 
 
 def horizons(w: Workload):
