@@ -346,6 +346,13 @@ int hjg_surrogate_set_params(hjg_surrogate* s, const float* params, const float*
 /* Copy parameters (and, if norm != NULL, the normalisation) to host memory.
  * Synchronous. */
 int hjg_surrogate_get_params(const hjg_surrogate* s, float* params, float* norm);
+/* Write the network (shape, parameters in the exchange format, normalisation)
+ * to a binary file; synchronous.  HJG_EINVAL on NULL or an I/O failure. */
+int hjg_surrogate_save(const hjg_surrogate* s, const char* path);
+/* Create a surrogate on the context's device from a file written by
+ * hjg_surrogate_save (optimiser state reset).  HJG_EINVAL on NULL, an
+ * unreadable or foreign file, or sizes that disagree with its header. */
+int hjg_surrogate_load(hjg_ctx* ctx, const char* path, hjg_surrogate** out);
 /* Evaluate at Q states: x device [n][Q], t device [Q]; v device [Q] and grad
  * device [n][Q] out.  Asynchronous. */
 int hjg_surrogate_predict(hjg_surrogate* s, int64_t Q, const float* x,

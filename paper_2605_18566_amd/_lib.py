@@ -134,6 +134,8 @@ SIGNATURES = [
     ("hjg_topology", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     ("hjg_topology_events", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hjg_surrogate_save", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("hjg_surrogate_load", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_void_p)]),
     ("hjg_set_timing", C.c_int, [C.c_void_p, C.c_int32]),
     ("hjg_sweep_time", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("hjg_picard_sweep", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,

@@ -7,6 +7,7 @@ tensors, as in include/hjg.h.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
@@ -357,6 +358,22 @@ class Surrogate:
     @property
     def handle(self):
         return self._h
+
+    def save(self, path: str):
+        """Write shape, parameters and normalisation to a file (hjg_surrogate_save)."""
+        check(_lib.lib().hjg_surrogate_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "Surrogate":
+        """A surrogate from a file written by save (hjg_surrogate_load)."""
+        h = C.c_void_p()
+        check(_lib.lib().hjg_surrogate_load(ctx.handle, os.fsencode(path), C.byref(h)))
+        obj = cls.__new__(cls)
+        obj._h, obj.ctx = h, ctx
+        with open(path, "rb") as f:
+            hdr = np.frombuffer(f.read(24)[8:24], dtype=np.int32)
+        obj.n, obj.width, obj.depth = int(hdr[0]), int(hdr[1]), int(hdr[2])
+        return obj
 
     def param_count(self) -> int:
         c = C.c_int64(0)

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -391,6 +392,70 @@ int hjg_surrogate_get_params(const hjg_surrogate* s, float* params, float* norm)
     for (int o = 0; o < s->tout[l]; ++o) params[k++] = hw[s->boff[l] + o];
   }
   if (norm) SG_HIP(hipMemcpy(norm, s->norm.p, 4 * s->nin * 4, hipMemcpyDeviceToHost));
+  return HJG_OK;
+}
+
+// File layout (little-endian): the 8 bytes "HJGSURR1", int32 n, width, depth,
+// int32 0, int64 parameter count, float32 parameters (exchange format),
+// float32 normalisation [4][n + 1].
+int hjg_surrogate_save(const hjg_surrogate* s, const char* path) {
+  if (!s || !path) return fail(HJG_EINVAL, "NULL argument");
+  int64_t count = 0;
+  int rc = hjg_surrogate_param_count(s, &count);
+  if (rc) return rc;
+  std::vector<float> params((size_t)count), norm((size_t)4 * s->nin);
+  if ((rc = hjg_surrogate_get_params(s, params.data(), norm.data()))) return rc;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(HJG_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int32_t hdr[4] = {s->n, s->width, s->depth, 0};
+  bool ok = std::fwrite("HJGSURR1", 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 &&
+            std::fwrite(&count, 8, 1, f) == 1 && std::fwrite(params.data(), 4, params.size(), f) == params.size() &&
+            std::fwrite(norm.data(), 4, norm.size(), f) == norm.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(HJG_EINVAL, std::string("writing ") + path + " failed");
+  return HJG_OK;
+}
+
+int hjg_surrogate_load(hjg_ctx* ctx, const char* path, hjg_surrogate** out) {
+  if (!ctx || !path || !out) return fail(HJG_EINVAL, "NULL argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(HJG_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t hdr[4];
+  int64_t count = 0;
+  auto bad = [&](const std::string& why) {
+    std::fclose(f);
+    return fail(HJG_EINVAL, std::string(path) + ": " + why);
+  };
+  if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "HJGSURR1", 8) != 0) return bad("not a surrogate file");
+  if (std::fread(hdr, 4, 4, f) != 4 || std::fread(&count, 8, 1, f) != 1) return bad("truncated header");
+  hjg_surrogate* s = nullptr;
+  int rc = hjg_surrogate_create(ctx, hdr[0], hdr[1], hdr[2], 0, &s);
+  if (rc) {
+    std::fclose(f);
+    return rc;
+  }
+  int64_t expect = 0;
+  hjg_surrogate_param_count(s, &expect);
+  std::vector<float> params, norm((size_t)4 * s->nin);
+  bool ok = count == expect;
+  if (ok) {
+    params.resize((size_t)count);
+    char extra;
+    ok = std::fread(params.data(), 4, params.size(), f) == params.size() &&
+         std::fread(norm.data(), 4, norm.size(), f) == norm.size() && std::fread(&extra, 1, 1, f) == 0;
+  }
+  std::fclose(f);
+  if (!ok) {
+    hjg_surrogate_destroy(s);
+    return fail(HJG_EINVAL, std::string(path) + ": parameter count or size does not match the header");
+  }
+  if ((rc = hjg_surrogate_set_params(s, params.data(), norm.data()))) {
+    hjg_surrogate_destroy(s);
+    return rc;
+  }
+  *out = s;
   return HJG_OK;
 }
 

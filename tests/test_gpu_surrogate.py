@@ -255,3 +255,30 @@ def test_recorded_training_steps_match_direct_launches(ctx, monkeypatch):
         sur.close()
     np.testing.assert_array_equal(params[0], params[1])
     np.testing.assert_array_equal(hists[0], hists[1])
+
+
+def test_save_load_round_trip_and_bad_files(ctx, tmp_path):
+    from paper_2605_18566_amd import Surrogate, _lib
+    sizes, layers, norm = random_net(5, 64, 2, 21)
+    sur = Surrogate(ctx, 5, 64, 2)
+    sur.set_params(flat_from_layers(layers), norm)
+    path = str(tmp_path / "net.hjgs")
+    sur.save(path)
+    back = Surrogate.load(ctx, path)
+    assert (back.n, back.width, back.depth) == (5, 64, 2)
+    p0, n0 = sur.get_params()
+    p1, n1 = back.get_params()
+    np.testing.assert_array_equal(p0, p1)
+    np.testing.assert_array_equal(n0, n1)
+    x = to_dev(np.random.default_rng(1).normal(0, 1, (5, 300)))
+    va, ga = sur.predict(x, 0.5)
+    vb, gb = back.predict(x, 0.5)
+    assert torch.equal(va, vb) and torch.equal(ga, gb)
+    raw = open(path, "rb").read()
+    for name, data in (("foreign", b"NOTASURR" + raw[8:]), ("truncated", raw[:-4]), ("trailing", raw + b"\0")):
+        bad = tmp_path / name
+        bad.write_bytes(data)
+        with pytest.raises(_lib.HJGError):
+            Surrogate.load(ctx, str(bad))
+    sur.close()
+    back.close()

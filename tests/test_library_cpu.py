@@ -88,6 +88,9 @@ def test_version_and_error_paths_without_device(lib):
     rc = lib.hjg_surrogate_tube_step(None, None, C.byref(p), 4, None, 0.0, 0.1, 16, 1, 0.0, 0, None, None, None,
                                      None, None, None, None)
     assert rc == _lib.HJG_EINVAL and b"surrogate" in lib.hjg_last_error()
+    h = C.c_void_p()
+    assert lib.hjg_surrogate_load(None, b"/nonexistent/x", C.byref(h)) == _lib.HJG_EINVAL
+    assert lib.hjg_surrogate_save(None, b"/nonexistent/x") == _lib.HJG_EINVAL
     assert lib.hjg_tuning_save(None, b"/nonexistent/x") == _lib.HJG_EINVAL
     assert lib.hjg_tuning_load(None, b"/nonexistent/x") == _lib.HJG_EINVAL
     lib.hjg_ctx_destroy(None)
