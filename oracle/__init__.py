@@ -38,6 +38,8 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   topology.markers / events      : hand-built slices of plain topology (discs,
                                    rings, holes open to the border, diagonal
                                    contact) and a hand-made event sequence
+  contour.segments               : exact on linear fields, circle length and
+                                   radius, the two saddle cells by hand
   model.hamiltonian (Dubins,     : brute-force max-min over control grids
     multi-pursuer game)
   model.coefficient              : direct evaluation checks (sign, clip, eta)
