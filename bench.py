@@ -528,7 +528,7 @@ def topology_study(ctx, stream):
     import torch
 
     import workloads
-    from paper_2605_18566_amd import ProblemSpec, picard_sweep, topology, topology_events
+    from paper_2605_18566_amd import ProblemSpec, isocontour, picard_sweep, topology, topology_events
     w = workloads.C2
     m = 128
     g = np.linspace(-3.0, 3.0, m)
@@ -549,6 +549,9 @@ def topology_study(ctx, stream):
         nc, b1, chi = topology(v, stream=stream)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
+        seg, sl = isocontour(v, 0.0, stream=stream)
+        seg_len = torch.linalg.vector_norm(seg[:, 2:] - seg[:, :2], dim=1) * (6.0 / (m - 1))
+        perimeter = [float(seg_len[sl == j].sum()) for j in range(len(vs))]
     nc, b1, chi = nc.cpu().numpy(), b1.cpu().numpy(), chi.cpu().numpy()
     ev = topology_events(chi, b1, nc)
     names = {1: "vacuole", 2: "cordon", 4: "fragmentation"}
@@ -557,6 +560,8 @@ def topology_study(ctx, stream):
             "n_comp": nc.tolist(), "beta1": b1.tolist(), "chi": chi.tolist(),
             "inside_fraction": [float((vv <= 0).float().mean()) for vv in vs],
             "events": [[names[b] for b in (1, 2, 4) if e & b] for e in ev.tolist()],
+            "zero_level_contour_length": perimeter,
+            "zero_level_contour_length_disc": 2 * 3.141592653589793 * 0.5,
             "topology_ms_for_all_slices": ms}
 
 

@@ -479,6 +479,19 @@ enum { HJG_EVENT_VACUOLE = 1, HJG_EVENT_CORDON = 2, HJG_EVENT_FRAGMENTATION = 4 
  * NULL, HJG_EUNSUPPORTED for larger slices. */
 int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v,
                  int32_t* n_comp, int32_t* beta1, int32_t* chi, void* hip_stream);
+/* Marching-squares isocontours of v = level on B slices (v device float32
+ * [B][ny][nx]): cell (x, y) has corners c0 = (x, y), c1 = (x+1, y),
+ * c2 = (x+1, y+1), c3 = (x, y+1); a corner is inside when v <= level; each
+ * crossed edge is cut at the linear interpolation point; a cell with two
+ * crossed edges gives one segment, the two saddle cells two, joined through
+ * the cell centre when the mean of the corners is inside.  Segments go to
+ * seg device float32 [max_seg][4] as (x0, y0, x1, y1) in (column, row) grid
+ * units, with their slice in seg_slice device int32 [max_seg] (or NULL), in
+ * no particular order; count device int64 [1] receives the total found,
+ * which may exceed max_seg (then only max_seg were written).  Asynchronous. */
+int hjg_isocontour(int32_t B, int32_t ny, int32_t nx, const float* v, float level,
+                   float* seg, int32_t* seg_slice, int64_t max_seg, int64_t* count,
+                   void* hip_stream);
 /* Event bits per step from the markers of T consecutive steps (host arrays):
  * HJG_EVENT_VACUOLE where chi[t] - chi[t-1] < -0.5, HJG_EVENT_CORDON where
  * beta1[t] >= 1 and beta1[t-1] == 0, HJG_EVENT_FRAGMENTATION where

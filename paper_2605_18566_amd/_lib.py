@@ -134,6 +134,8 @@ SIGNATURES = [
     ("hjg_topology", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     ("hjg_topology_events", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hjg_isocontour", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p]),
     ("hjg_surrogate_save", C.c_int, [C.c_void_p, C.c_char_p]),
     ("hjg_surrogate_load", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_void_p)]),
     ("hjg_set_timing", C.c_int, [C.c_void_p, C.c_int32]),

@@ -529,3 +529,24 @@ def topology_events(chi, beta1, n_comp) -> np.ndarray:
     check(_lib.lib().hjg_topology_events(T, chi.ctypes.data, beta1.ctypes.data, n_comp.ctypes.data,
                                          ev.ctypes.data))
     return ev
+
+
+def isocontour(v: torch.Tensor, level: float = 0.0, max_seg: Optional[int] = None, stream=None):
+    """Marching-squares segments of v = level on slices v [B, ny, nx] (or [ny, nx]):
+    (seg [S, 4] as (x0, y0, x1, y1) in grid units, slice [S]); grows the buffer and
+    repeats if more than max_seg were found."""
+    _require_cuda(v, "v")
+    if v.dim() == 2:
+        v = v.unsqueeze(0)
+    B, ny, nx = v.shape
+    cap = int(max_seg) if max_seg is not None else max(1024, 4 * B * (ny + nx))
+    count = torch.zeros(1, dtype=torch.int64, device=v.device)
+    while True:
+        seg = torch.empty((cap, 4), dtype=torch.float32, device=v.device)
+        sl = torch.empty(cap, dtype=torch.int32, device=v.device)
+        check(_lib.lib().hjg_isocontour(B, ny, nx, _ptr(v), float(level), _ptr(seg), _ptr(sl), cap, _ptr(count),
+                                        _stream(stream)))
+        n = int(count.item())
+        if n <= cap:
+            return seg[:n], sl[:n]
+        cap = n

@@ -86,9 +86,100 @@ __global__ __launch_bounds__(kTT) void topology_kernel(int ny, int nx, const flo
   }
 }
 
+// Marching squares: one thread per cell.  Corners c0 = (x, y), c1 = (x+1, y),
+// c2 = (x+1, y+1), c3 = (x, y+1); edges e0 = c0-c1, e1 = c1-c2, e2 = c2-c3,
+// e3 = c3-c0; a corner is inside when v <= level; a crossed edge is cut at
+// the linear interpolation point; the saddle cells are decided by the mean of
+// the four corners.  Segments are appended through a global counter.
+__device__ __forceinline__ float2 edge_point(int e, const float* c, float level, int x, int y) {
+  const int a = e, b = (e + 1) & 3;
+  const float cx[4] = {0.f, 1.f, 1.f, 0.f}, cy[4] = {0.f, 0.f, 1.f, 1.f};
+  const float t = fminf(fmaxf((level - c[a]) / (c[b] - c[a]), 0.f), 1.f);
+  return make_float2((float)x + cx[a] + t * (cx[b] - cx[a]), (float)y + cy[a] + t * (cy[b] - cy[a]));
+}
+
+__global__ __launch_bounds__(256) void isocontour_kernel(int64_t total, int ny, int nx, const float* v, float level,
+                                                         float* seg, int* seg_slice, int64_t max_seg,
+                                                         unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t cells = (int64_t)(ny - 1) * (nx - 1);
+  const int b = (int)(i / cells);
+  const int64_t cc = i % cells;
+  const int y = (int)(cc / (nx - 1)), x = (int)(cc % (nx - 1));
+  const float* vs = v + (int64_t)b * ny * nx;
+  const float c[4] = {vs[(int64_t)y * nx + x], vs[(int64_t)y * nx + x + 1], vs[(int64_t)(y + 1) * nx + x + 1],
+                      vs[(int64_t)(y + 1) * nx + x]};
+  int in = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) in |= (c[k] <= level ? 1 : 0) << k;
+  if (in == 0 || in == 15) return;
+  int pa[2], pb[2], np = 0;
+  if (in == 5 || in == 10) {
+    const bool centre_in = 0.25f * (c[0] + c[1] + c[2] + c[3]) <= level;
+    // cut off the outside corners if the centre is inside, else the inside ones;
+    // the edges meeting at corner k are e(k-1) and e(k)
+    for (int k = 0; k < 4; ++k) {
+      const bool corner_in = (in >> k) & 1;
+      if (corner_in != centre_in) {
+        pa[np] = (k + 3) & 3;
+        pb[np] = k;
+        ++np;
+      }
+    }
+  } else {
+    int e0 = -1;
+    for (int e = 0; e < 4; ++e) {
+      if (((in >> e) & 1) != ((in >> ((e + 1) & 3)) & 1)) {
+        if (e0 < 0) e0 = e;
+        else {
+          pa[0] = e0;
+          pb[0] = e;
+          np = 1;
+        }
+      }
+    }
+  }
+  for (int k = 0; k < np; ++k) {
+    const float2 p = edge_point(pa[k], c, level, x, y), q = edge_point(pb[k], c, level, x, y);
+    const unsigned long long slot = atomicAdd(count, 1ull);
+    if ((int64_t)slot < max_seg) {
+      *reinterpret_cast<float4*>(seg + 4 * slot) = make_float4(p.x, p.y, q.x, q.y);
+      if (seg_slice) seg_slice[slot] = b;
+    }
+  }
+}
+
+__global__ void zero_count_kernel(unsigned long long* c) {
+  if (threadIdx.x == 0) *c = 0ull;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hjg_isocontour(int32_t B, int32_t ny, int32_t nx, const float* v, float level, float* seg, int32_t* seg_slice,
+                   int64_t max_seg, int64_t* count, void* hip_stream) {
+  if (B < 0 || ny < 1 || nx < 1 || max_seg < 0) return fail(HJG_EINVAL, "need B >= 0, a grid of at least 1 x 1, max_seg >= 0");
+  if ((int64_t)B * ny * nx > ((int64_t)1 << 40)) return fail(HJG_EINVAL, "too many grid values");
+  if (!count) return fail(HJG_EINVAL, "count is required");
+  if (max_seg > 0 && !seg) return fail(HJG_EINVAL, "seg is required when max_seg > 0");
+  if (B > 0 && !v) return fail(HJG_EINVAL, "v is required");
+  hipStream_t st = (hipStream_t)hip_stream;
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(count);
+  zero_count_kernel<<<1, 64, 0, st>>>(cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HJG_EHIP, std::string("isocontour: ") + hipGetErrorString(e));
+  const int64_t total = (int64_t)B * (ny - 1) * (nx - 1);
+  if (total > 0) {
+    isocontour_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(total, ny, nx, v, level, seg, seg_slice,
+                                                                       max_seg, cnt);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(HJG_EHIP, std::string("isocontour: ") + hipGetErrorString(e));
+  }
+  return HJG_OK;
+}
+
 
 int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v, int32_t* n_comp, int32_t* beta1, int32_t* chi,
                  void* hip_stream) {
