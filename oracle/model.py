@@ -15,15 +15,17 @@ from typing import Optional
 
 import numpy as np
 
-HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator", "pursuit_evasion", "rockets")
-DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear", "capture")
+HAMILTONIANS = ("quadratic", "dubins_pairs", "zero", "double_integrator", "pursuit_evasion", "rockets",
+                "murmuration")
+DATUMS = ("half_sqnorm", "ball", "min_pair_disks", "knn_balls", "linear", "capture", "disc_union")
 
 
 @dataclass
 class Problem:
     """One problem instance; mirrors the fields of the library's problem record.
 
-    ham_p:   rockets: (a, g, u_max).  quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
+    ham_p:   rockets: (a, g, u_max).  murmuration: (v_e, v_p, w_e, w_p,
+             g_lo, g_hi).  quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
              sign of the p2 term (+1 from the relative dynamics, -1 for the form
              the paper prints).  double_integrator: (u_max,).
              pursuit_evasion: (a_evader, a_pursuer, u_max) for m = n/3 planar
@@ -32,6 +34,7 @@ class Problem:
              min_pair_disks: (r,).  knn_balls: (r, K).  linear: (b,).
              capture: (r,) -> min over pursuers of the distance to the evader, - r.
     datum_aux: linear: a[n].  knn_balls: neighbour positions [Q, K, 3].
+             disc_union: the K planar centres [K, 2] (datum_p = (r, K)).
     """
     n: int
     ham: str
@@ -92,6 +95,13 @@ def datum(pb: Problem, y: np.ndarray, q_aux: Optional[np.ndarray] = None) -> np.
         e = 3 * (m - 1)
         d2 = (y[..., 0:e:3] - y[..., e:e + 1]) ** 2 + (y[..., 1:e:3] - y[..., e + 1:e + 2]) ** 2
         return np.sqrt(np.min(d2, axis=-1)) - r
+    if kind == "disc_union":
+        # union of capture cylinders about fixed planar centres (appendix,
+        # murmuration setup): min_j |(y0, y1) - c_j| - r
+        r = float(pb.datum_p[0])
+        cen = np.asarray(pb.datum_aux, dtype=np.float64).reshape(-1, 2)
+        d2 = (y[..., 0:1] - cen[:, 0]) ** 2 + (y[..., 1:2] - cen[:, 1]) ** 2
+        return np.sqrt(np.min(d2, axis=-1)) - r
     raise ValueError(f"unknown datum {kind}")
 
 
@@ -150,6 +160,17 @@ def datum_grad(pb: Problem, x: np.ndarray, aux_all: Optional[np.ndarray] = None)
         g[:, e] = -gx
         g[:, e + 1] = -gy
         return g
+    if kind == "disc_union":
+        cen = np.asarray(pb.datum_aux, dtype=np.float64).reshape(-1, 2)
+        dx = x[:, 0:1] - cen[:, 0]
+        dy = x[:, 1:2] - cen[:, 1]
+        d2 = dx * dx + dy * dy
+        j = np.argmin(d2, axis=1)                          # first minimum
+        rho = np.sqrt(d2[np.arange(Q), j])
+        safe = np.where(rho > 0, rho, 1.0)
+        g[:, 0] = np.where(rho > 0, dx[np.arange(Q), j] / safe, 0.0)
+        g[:, 1] = np.where(rho > 0, dy[np.arange(Q), j] / safe, 0.0)
+        return g
     raise ValueError(f"unknown datum {kind}")
 
 
@@ -197,6 +218,17 @@ def hamiltonian(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
         p1, p2, p3 = p[:, 0], p[:, 1], p[:, 2]
         inner = a * p1 * np.cos(th) + p2 * (a + a * np.sin(th) - g)
         return -(inner + umax * np.abs(p1 * xx - p3) - umax * np.abs(p2 * xx + p3))
+    if kind == "murmuration":
+        # the individual under attack in a flock (appendix, murmuration
+        # Hamiltonian), relative state (x1, x2, altitude x3, heading x4), as
+        # printed in its general form:
+        # p1 (v_e - v_p cos x4) - p2 v_p sin x4 - w_p |p4|
+        #   + w_e |p2 x1 - p1 x2 + p4| + g_lo |p3| - g_hi |p3|
+        ve, vp, we, wp, glo, ghi = (float(v) for v in pb.ham_p[:6])
+        x1, x2, x4 = x[:, 0], x[:, 1], x[:, 3]
+        p1, p2, p3, p4 = p[:, 0], p[:, 1], p[:, 2], p[:, 3]
+        return (p1 * (ve - vp * np.cos(x4)) - p2 * vp * np.sin(x4) - wp * np.abs(p4)
+                + we * np.abs(p2 * x1 - p1 * x2 + p4) + glo * np.abs(p3) - ghi * np.abs(p3))
     if kind == "double_integrator":
         # pos' = vel, vel' = u with ||u|| <= u_max, the agent maximising.
         umax = float(pb.ham_p[0])

@@ -327,6 +327,47 @@ def test_rockets_hamiltonian_brute_force():
         np.testing.assert_allclose(model.hamiltonian(pb, x[None], p[None])[0], brute, rtol=1e-12, atol=1e-9)
 
 
+def test_murmuration_hamiltonian_planar_part_brute_force():
+    # the planar part is -max over the bird's turn rate u_e in [-w_e, w_e] of
+    # min over the predator's u_p in [-w_p, w_p] of <p, f> with
+    # x1' = v_e - v_p cos x4 - u_e x2, x2' = -v_p sin x4 + u_e x1, x4' = u_e - u_p
+    # (the dynamics whose max-min gives the printed terms); the altitude term
+    # g_lo |p3| - g_hi |p3| is taken as printed
+    rng = np.random.default_rng(14)
+    ve, vp, we, wp, glo, ghi = 1.0, 1.2, 0.8, 1.5, -0.3, 0.3
+    pb = model.Problem(n=4, ham="murmuration", datum="disc_union", datum_p=(0.6, 7), nu=0.09,
+                       ham_p=(ve, vp, we, wp, glo, ghi))
+    ue = np.linspace(-we, we, 61)
+    up = np.linspace(-wp, wp, 61)
+    for _ in range(6):
+        x = np.concatenate([rng.uniform(-3, 3, 3), rng.uniform(-np.pi, np.pi, 1)])
+        p = rng.standard_normal(4)
+        UE, UP = np.meshgrid(ue, up, indexing="ij")
+        f1 = ve - vp * np.cos(x[3]) - UE * x[1]
+        f2 = -vp * np.sin(x[3]) + UE * x[0]
+        f4 = UE - UP
+        val = p[0] * f1 + p[1] * f2 + p[3] * f4
+        brute = np.max(np.min(val, axis=1)) + (glo - ghi) * abs(p[2])
+        np.testing.assert_allclose(model.hamiltonian(pb, x[None], p[None])[0], brute, rtol=1e-12, atol=1e-9)
+
+
+def test_disc_union_datum_and_gradient():
+    cen = np.array([[1.15, 0.0], [0.0, 1.15], [-1.15, 0.0]])
+    pb = model.Problem(n=4, ham="murmuration", datum="disc_union", datum_p=(0.6, 3), nu=0.09, datum_aux=cen)
+    x = np.array([[1.15, 0.3, 5.0, 1.0], [0.0, 0.0, 0.0, 0.0], [2.0, 1.5, -1.0, 0.3]])
+    ell = model.datum(pb, x[:, None, :])[:, 0]
+    np.testing.assert_allclose(ell, [0.3 - 0.6, 1.15 - 0.6, np.hypot(0.85, 1.5) - 0.6])
+    g = model.datum_grad(pb, x)
+    h = 1e-6
+    for q in (0, 2):                                      # away from ties: central differences
+        for d in range(4):
+            e = np.zeros(4)
+            e[d] = h
+            fd = (model.datum(pb, (x[q] + e)[None, None]) - model.datum(pb, (x[q] - e)[None, None]))[0, 0] / (2 * h)
+            assert abs(fd - g[q, d]) < 1e-6
+    np.testing.assert_array_equal(g[1], [-1.0, 0.0, 0.0, 0.0])   # equidistant: the first centre wins
+
+
 def test_coefficient_sign_clip_and_regularisation():
     pb = model.Problem(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01,
                        eta=0.01, c_min=0.5, c_max=20.0)
