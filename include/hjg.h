@@ -79,13 +79,19 @@ enum hjg_ham {
                                 sum_j a_j (p_xj cos th_j + p_yj sin th_j)
                                 + u_max |p_th,evader| - u_max sum_pursuers |p_th,j|;
                                 ham_p = {a_evader, a_pursuer, u_max}; 2 <= m <= 16 */
-  HJG_H_ROCKETS = 5          /* two rockets on a plane (appendix, game of two rockets),
+  HJG_H_ROCKETS = 5,         /* two rockets on a plane (appendix, game of two rockets),
                                 n = 3, x = (x, z, theta) relative: with the rows of
                                 its Hamiltonian definition eq. (ham_general),
                                 H = -[a p1 cos th + p2 (a + a sin th - g)
                                       + u_max |p1 x - p3| - u_max |p2 x + p3|]
                                 (evader u_e maximises, pursuer u_p minimises,
                                 |u| <= u_max); ham_p = {a, g, u_max}              */
+  HJG_H_MURMURATION = 6      /* the individual under attack in a flock (appendix,
+                                murmuration Hamiltonian, general printed form),
+                                n = 4, x = (x1, x2, altitude, heading) relative:
+                                p1 (v_e - v_p cos x4) - p2 v_p sin x4 - w_p |p4|
+                                + w_e |p2 x1 - p1 x2 + p4| + g_lo |p3| - g_hi |p3|;
+                                ham_p = {v_e, v_p, w_e, w_p, g_lo, g_hi}          */
 };
 
 /* Terminal data l(y) (signed distance: negative inside the target set). */
@@ -98,10 +104,14 @@ enum hjg_datum {
                                 neighbour positions; datum_p = {r, K}, K <= 8;
                                 datum_aux = device [K][3][Q]                          */
   HJG_L_LINEAR = 4,          /* <a, y> + b; datum_p = {b}; datum_aux = device a[n]     */
-  HJG_L_CAPTURE = 5          /* min over pursuers j of |(y[3j], y[3j+1]) - evader
+  HJG_L_CAPTURE = 5,         /* min over pursuers j of |(y[3j], y[3j+1]) - evader
                                 position| - r, the evader being the last of the
                                 m = n/3 agents (capture set of the Section 3.2 game);
                                 datum_p = {r}; 2 <= m <= 16                           */
+  HJG_L_DISC_UNION = 6       /* min_j |(y[0], y[1]) - c_j| - r over K fixed planar
+                                centres shared by every state (union of capture
+                                cylinders, murmuration setup); datum_p = {r, K},
+                                K <= 8; datum_aux = device [K][2]; 2 <= n <= 16  */
 };
 
 /* Where the draws come from. */
@@ -115,7 +125,7 @@ enum hjg_sample_mode {
 typedef struct hjg_problem {
   int32_t n;               /* state dimension, 1..48                               */
   int32_t ham;             /* enum hjg_ham                                          */
-  double ham_p[4];
+  double ham_p[8];          /* Hamiltonian parameters (see hjg_ham; unused entries 0) */
   int32_t datum;           /* enum hjg_datum                                        */
   double datum_p[4];
   const float* datum_aux;  /* device; see hjg_datum, else NULL                      */
@@ -492,6 +502,14 @@ int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v,
 int hjg_isocontour(int32_t B, int32_t ny, int32_t nx, const float* v, float level,
                    float* seg, int32_t* seg_slice, int64_t max_seg, int64_t* count,
                    void* hip_stream);
+/* Gaussian smoothing of B slices before the markers are read (the paper
+ * smooths its slices' sampling speckle): out = v convolved along rows and then
+ * columns with the normalised Gaussian of standard deviation sigma cells,
+ * truncated at round(4 sigma) cells, mirror extension about the outer cell
+ * edges.  v, out device float32 [B][ny][nx] (distinct), ny nx <= 16,384,
+ * sigma in (0, 8].  Asynchronous. */
+int hjg_smooth_slices(int32_t B, int32_t ny, int32_t nx, const float* v,
+                      double sigma, float* out, void* hip_stream);
 /* Event bits per step from the markers of T consecutive steps (host arrays):
  * HJG_EVENT_VACUOLE where chi[t] - chi[t-1] < -0.5, HJG_EVENT_CORDON where
  * beta1[t] >= 1 and beta1[t-1] == 0, HJG_EVENT_FRAGMENTATION where

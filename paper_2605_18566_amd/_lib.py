@@ -15,8 +15,9 @@ LIB_PATH = os.path.join(HERE, "libhjg.so")
 HJG_OK, HJG_ENOTCONVERGED = 0, 1
 HJG_EINVAL, HJG_ENOMEM, HJG_EHIP, HJG_ENONFINITE, HJG_EUNSUPPORTED = -1, -2, -3, -4, -5
 HAMILTONIANS = {"quadratic": 0, "dubins_pairs": 1, "zero": 2, "double_integrator": 3, "pursuit_evasion": 4,
-                "rockets": 5}
-DATUMS = {"half_sqnorm": 0, "ball": 1, "min_pair_disks": 2, "knn_balls": 3, "linear": 4, "capture": 5}
+                "rockets": 5, "murmuration": 6}
+DATUMS = {"half_sqnorm": 0, "ball": 1, "min_pair_disks": 2, "knn_balls": 3, "linear": 4, "capture": 5,
+          "disc_union": 6}
 SAMPLE_MODES = {"fresh": 0, "crn_step": 1}
 
 
@@ -24,7 +25,7 @@ class Problem(C.Structure):
     _fields_ = [
         ("n", C.c_int32),
         ("ham", C.c_int32),
-        ("ham_p", C.c_double * 4),
+        ("ham_p", C.c_double * 8),
         ("datum", C.c_int32),
         ("datum_p", C.c_double * 4),
         ("datum_aux", C.c_void_p),
@@ -134,6 +135,8 @@ SIGNATURES = [
     ("hjg_topology", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p]),
     ("hjg_topology_events", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hjg_smooth_slices", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_double, C.c_void_p,
+                                    C.c_void_p]),
     ("hjg_isocontour", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p]),
     ("hjg_surrogate_save", C.c_int, [C.c_void_p, C.c_char_p]),

@@ -44,10 +44,13 @@ class ProblemSpec:
         p.n = self.n
         p.ham = _lib.HAMILTONIANS[self.ham]
         p.datum = _lib.DATUMS[self.datum]
-        hp = list(self.ham_p) + [0.0] * (4 - len(self.ham_p))
+        if len(self.ham_p) > 8 or len(self.datum_p) > 4:
+            raise ValueError("at most 8 Hamiltonian and 4 datum parameters")
+        hp = list(self.ham_p) + [0.0] * (8 - len(self.ham_p))
         dp = list(self.datum_p) + [0.0] * (4 - len(self.datum_p))
-        for i in range(4):
+        for i in range(8):
             p.ham_p[i] = float(hp[i])
+        for i in range(4):
             p.datum_p[i] = float(dp[i])
         if self.datum_aux is not None:
             _require_cuda(self.datum_aux, "datum_aux")
@@ -550,3 +553,15 @@ def isocontour(v: torch.Tensor, level: float = 0.0, max_seg: Optional[int] = Non
         if n <= cap:
             return seg[:n], sl[:n]
         cap = n
+
+
+def smooth_slices(v: torch.Tensor, sigma: float, stream=None) -> torch.Tensor:
+    """Gaussian smoothing (sigma in cells) of slices v [B, ny, nx] (or [ny, nx])."""
+    _require_cuda(v, "v")
+    squeeze = v.dim() == 2
+    if squeeze:
+        v = v.unsqueeze(0)
+    B, ny, nx = v.shape
+    out = torch.empty_like(v)
+    check(_lib.lib().hjg_smooth_slices(B, ny, nx, _ptr(v), float(sigma), _ptr(out), _stream(stream)))
+    return out[0] if squeeze else out

@@ -154,6 +154,11 @@ int check_problem(const hjg_problem* p) {
         if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
       if (!(p->ham_p[2] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
       break;
+    case HJG_H_MURMURATION:
+      if (p->n != 4) return fail(HJG_EINVAL, "the murmuration Hamiltonian needs n = 4");
+      for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(p->ham_p[i])) return fail(HJG_EINVAL, "ham_p must be finite");
+      break;
     case HJG_H_ROCKETS:
       if (p->n != 3) return fail(HJG_EINVAL, "the rockets game needs n = 3");
       for (int i = 0; i < 3; ++i)
@@ -192,6 +197,14 @@ int check_problem(const hjg_problem* p) {
       if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
       break;
     }
+    case HJG_L_DISC_UNION: {
+      const double k = p->datum_p[1];
+      if (p->n < 2 || p->n > 16) return fail(HJG_EINVAL, "disc_union needs 2 <= n <= 16");
+      if (!(k >= 1 && k <= kMaxKnn && k == std::floor(k))) return fail(HJG_EINVAL, "disc_union: K in [1, 8]");
+      if (!p->datum_aux) return fail(HJG_EINVAL, "disc_union needs datum_aux = centres [K][2]");
+      if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "radius must be finite");
+      break;
+    }
     case HJG_L_LINEAR:
       if (!p->datum_aux) return fail(HJG_EINVAL, "linear datum needs datum_aux = a[n]");
       if (!std::isfinite(p->datum_p[0])) return fail(HJG_EINVAL, "offset must be finite");
@@ -215,6 +228,7 @@ DatumP datum_params(const hjg_problem* p) {
     case HJG_L_MIN_PAIR_DISKS: d.r = (float)p->datum_p[0]; break;
     case HJG_L_CAPTURE: d.r = (float)p->datum_p[0]; break;
     case HJG_L_KNN_BALLS: d.r = (float)p->datum_p[0]; d.k = (int)p->datum_p[1]; break;
+    case HJG_L_DISC_UNION: d.r = (float)p->datum_p[0]; d.k = (int)p->datum_p[1]; break;
     case HJG_L_LINEAR: d.r = (float)p->datum_p[0]; break;
     default: break;
   }
@@ -225,7 +239,7 @@ HamP ham_params(const hjg_problem* p) {
   HamP h;
   h.kind = p->ham;
   h.n = p->n;
-  for (int i = 0; i < 4; ++i) h.p[i] = (float)p->ham_p[i];
+  for (int i = 0; i < 6; ++i) h.p[i] = (float)p->ham_p[i];
   const double delta = 2.0 * p->nu;
   h.inv_delta = (float)(1.0 / delta);
   h.two_over_delta = (float)(2.0 / delta);
@@ -243,7 +257,8 @@ uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter) { return (pid << 1
 bool use_mfma(const hjg_problem* p) {
   const char* e = std::getenv("HJG_NO_MFMA");
   if (e && e[0] == '1') return false;
-  return p->sample_mode == HJG_S_CRN_STEP && p->sample_bf16 && p->n >= 16 && p->datum != HJG_L_KNN_BALLS;
+  return p->sample_mode == HJG_S_CRN_STEP && p->sample_bf16 && p->n >= 16 && p->datum != HJG_L_KNN_BALLS &&
+         p->datum != HJG_L_DISC_UNION;
 }
 
 // Stacked disc pairs on the matrix cores use the one-query-per-lane kernel,
@@ -560,10 +575,8 @@ void copy_problem(hjg_problem* dst, const hjg_problem* src) {
   dst->n = src->n;
   dst->ham = src->ham;
   dst->datum = src->datum;
-  for (int i = 0; i < 4; ++i) {
-    dst->ham_p[i] = src->ham_p[i];
-    dst->datum_p[i] = src->datum_p[i];
-  }
+  for (int i = 0; i < 8; ++i) dst->ham_p[i] = src->ham_p[i];
+  for (int i = 0; i < 4; ++i) dst->datum_p[i] = src->datum_p[i];
   dst->datum_aux = src->datum_aux;
   dst->nu = src->nu;
   dst->eta = src->eta;

@@ -79,7 +79,7 @@ struct DatumP {
 struct HamP {
   int kind;       // enum hjg_ham
   int n;
-  float p[4];
+  float p[6];
   float inv_delta;      // 1 / delta
   float two_over_delta; // 2 / delta
   float eta, c_min, c_max;
@@ -139,6 +139,17 @@ __device__ inline float datum_and_grad(const DatumP& dp, const float* x, float* 
       }
       const float rho = sqrtf(best);
       if (rho > 0.f) { g[0] = b0 / rho; g[1] = b1 / rho; g[2] = b2 / rho; }
+      return rho - dp.r;
+    }
+    case HJG_L_DISC_UNION: {
+      float best = INFINITY, b0 = 0.f, b1 = 0.f;
+      for (int j = 0; j < dp.k; ++j) {
+        const float e0 = x[0] - dp.aux[2 * j], e1 = x[1] - dp.aux[2 * j + 1];
+        const float r2 = e0 * e0 + e1 * e1;
+        if (r2 < best) { best = r2; b0 = e0; b1 = e1; }
+      }
+      const float rho = sqrtf(best);
+      if (rho > 0.f) { g[0] = b0 / rho; g[1] = b1 / rho; }
       return rho - dp.r;
     }
     case HJG_L_CAPTURE: {
@@ -220,6 +231,13 @@ __device__ inline float hamiltonian(const HamP& hp, const float* x, const float*
     case HJG_H_DOUBLE_INTEGRATOR: {
       const float pv = sqrtf(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
       return p[0] * x[3] + p[1] * x[4] + p[2] * x[5] + hp.p[0] * pv;
+    }
+    case HJG_H_MURMURATION: {
+      const float ve = hp.p[0], vp = hp.p[1], we = hp.p[2], wp = hp.p[3], glo = hp.p[4], ghi = hp.p[5];
+      float s4, c4;
+      sincosf(x[3], &s4, &c4);
+      return p[0] * (ve - vp * c4) - p[1] * vp * s4 - wp * fabsf(p[3]) + we * fabsf(p[1] * x[0] - p[0] * x[1] + p[3]) +
+             (glo - ghi) * fabsf(p[2]);
     }
     case HJG_H_ROCKETS: {
       // relative rockets: x' = a cos th + u_e x, z' = a sin th + a + u_p x - g,

@@ -12,6 +12,7 @@ hipError_t launch_sweep_ball(const SweepArgs&, int, int, hipStream_t, const Swee
 hipError_t launch_sweep_min_pair_disks(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
 hipError_t launch_sweep_knn_balls(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
 hipError_t launch_sweep_capture(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
+hipError_t launch_sweep_disc_union(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
 hipError_t launch_sweep_linear(const SweepArgs&, int, int, hipStream_t, const SweepBatch*);
 
 hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s, const SweepBatch* b) {
@@ -21,6 +22,7 @@ hipError_t launch_sweep(const SweepArgs& a, int fresh, int bf16, hipStream_t s, 
     case HJG_L_MIN_PAIR_DISKS: return launch_sweep_min_pair_disks(a, fresh, bf16, s, b);
     case HJG_L_KNN_BALLS: return launch_sweep_knn_balls(a, fresh, bf16, s, b);
     case HJG_L_CAPTURE: return launch_sweep_capture(a, fresh, bf16, s, b);
+    case HJG_L_DISC_UNION: return launch_sweep_disc_union(a, fresh, bf16, s, b);
     case HJG_L_LINEAR: return launch_sweep_linear(a, fresh, bf16, s, b);
     default: return hipErrorInvalidValue;
   }

@@ -33,7 +33,8 @@ template <int DATUM, int NM>
 struct PairConst {
   float u[NM];    // x + theta, the proposal mean (kFar on padded disc pairs)
   float tl[NM];   // log2(e) theta / sigma (LINEAR: also folds in the datum slope)
-  float nb[DATUM == HJG_L_KNN_BALLS ? 3 * kMaxKnn : 1];  // x + theta - neighbour, KNN
+  float nb[DATUM == HJG_L_KNN_BALLS ? 3 * kMaxKnn : (DATUM == HJG_L_DISC_UNION ? 2 * kMaxKnn : 1)];
+                  // x + theta - neighbour (KNN) or - planar centre (DISC_UNION)
   float sd[DATUM == HJG_L_BALL ? NM : 1];                // sigma on the ball's k coordinates, else 0
   float sg;       // sigma
   float cl;       // log2(e) c
@@ -65,6 +66,12 @@ __device__ __forceinline__ void pair_setup(PairConst<DATUM, NM>& P, const SweepA
 #pragma unroll
       for (int e = 0; e < 3; ++e)
         P.nb[3 * j + e] = (j < A.dp.k) ? P.u[e] - A.dp.aux[(int64_t)(3 * j + e) * A.Q + q] : kFar;
+  }
+  if constexpr (DATUM == HJG_L_DISC_UNION) {
+#pragma unroll
+    for (int j = 0; j < kMaxKnn; ++j)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) P.nb[2 * j + e] = (j < A.dp.k) ? P.u[e] - A.dp.aux[2 * j + e] : kFar;
   }
   if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
 #pragma unroll
@@ -155,6 +162,17 @@ __device__ __forceinline__ float pair_log2w(const PairConst<DATUM, NM>& P, const
     for (int j = 0; j < kMaxKnn; ++j) {
       const float e0 = P.nb[3 * j] + s0, e1 = P.nb[3 * j + 1] + s1, e2 = P.nb[3 * j + 2] + s2;
       best = fminf(best, fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
+    }
+#pragma unroll
+    for (int d = 0; d < NM; ++d) tz = fmaf(zf(d), P.tl[d], tz);
+    ell = __builtin_amdgcn_sqrtf(best) - dp.r;
+  } else if constexpr (DATUM == HJG_L_DISC_UNION) {
+    const float s0 = P.sg * zf(0), s1 = P.sg * zf(1);
+    float best = INFINITY;
+#pragma unroll
+    for (int j = 0; j < kMaxKnn; ++j) {
+      const float e0 = P.nb[2 * j] + s0, e1 = P.nb[2 * j + 1] + s1;
+      best = fminf(best, fmaf(e0, e0, e1 * e1));
     }
 #pragma unroll
     for (int d = 0; d < NM; ++d) tz = fmaf(zf(d), P.tl[d], tz);
@@ -387,7 +405,7 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
         sweep_pairs_kernel<NM, MP><<<grid, kPThreads, 0, s>>>(a);
       }
       return hipGetLastError();
-    } else if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS) {
+    } else if constexpr (NM >= 16 && DATUM != HJG_L_KNN_BALLS && DATUM != HJG_L_DISC_UNION) {
       if (fresh || !bf16) return hipErrorInvalidValue;
       if (b) {
         const unsigned g = batch_grid(sweep_mfma_batched_kernel<DATUM, NM, MP>, 256, b);
@@ -462,6 +480,13 @@ hipError_t launch_sweep_d(const SweepArgs& a, int fresh, int bf16, hipStream_t s
     }
   } else if constexpr (DATUM == HJG_L_KNN_BALLS) {
     return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s, b);
+  } else if constexpr (DATUM == HJG_L_DISC_UNION) {
+    switch (n_bucket(a.n)) {
+      case 4: return launch_sweep_dn<DATUM, 4, 0>(a, fresh, bf16, s, b);
+      case 8: return launch_sweep_dn<DATUM, 8, 0>(a, fresh, bf16, s, b);
+      case 16: return launch_sweep_dn<DATUM, 16, 0>(a, fresh, bf16, s, b);
+      default: return hipErrorInvalidValue;
+    }
   } else if constexpr (DATUM == HJG_L_MIN_PAIR_DISKS) {
     switch (a.n / 3) {
       case 1: return launch_pairs_exact<4, 1>(a, fresh, bf16, s, b);

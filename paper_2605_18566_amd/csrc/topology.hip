@@ -6,6 +6,7 @@
 // index and are set by atomic minimum, so concurrent unions keep a forest).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "hjg.h"
@@ -150,6 +151,43 @@ __global__ __launch_bounds__(256) void isocontour_kernel(int64_t total, int ny, 
   }
 }
 
+// Separable Gaussian smoothing of one slice per block in LDS: rows, then
+// columns, with mirror extension about the outer cell edges
+// (d c b a | a b c d | d c b a).
+constexpr int kMaxTaps = 65;
+struct SmoothTaps {
+  int radius;
+  float w[kMaxTaps];
+};
+
+__device__ __forceinline__ int mirror(int i, int n) {
+  while (i < 0 || i >= n) i = i < 0 ? -i - 1 : 2 * n - i - 1;
+  return i;
+}
+
+__global__ __launch_bounds__(kTT) void smooth_kernel(int ny, int nx, const float* v, SmoothTaps T, float* out) {
+  __shared__ float a[kMaxCells];
+  __shared__ float b[kMaxCells];
+  const int cells = ny * nx;
+  const float* vs = v + (int64_t)blockIdx.x * cells;
+  float* os = out + (int64_t)blockIdx.x * cells;
+  for (int i = threadIdx.x; i < cells; i += kTT) a[i] = vs[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < cells; i += kTT) {
+    const int x = i % nx, y = i / nx;
+    float acc = 0.f;
+    for (int k = -T.radius; k <= T.radius; ++k) acc = fmaf(T.w[k + T.radius], a[y * nx + mirror(x + k, nx)], acc);
+    b[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cells; i += kTT) {
+    const int x = i % nx, y = i / nx;
+    float acc = 0.f;
+    for (int k = -T.radius; k <= T.radius; ++k) acc = fmaf(T.w[k + T.radius], b[mirror(y + k, ny) * nx + x], acc);
+    os[i] = acc;
+  }
+}
+
 __global__ void zero_count_kernel(unsigned long long* c) {
   if (threadIdx.x == 0) *c = 0ull;
 }
@@ -190,6 +228,25 @@ int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v, int32_t* n_c
   topology_kernel<<<(unsigned)B, kTT, 0, (hipStream_t)hip_stream>>>(ny, nx, v, n_comp, beta1, chi);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HJG_EHIP, std::string("topology_kernel: ") + hipGetErrorString(e));
+  return HJG_OK;
+}
+
+int hjg_smooth_slices(int32_t B, int32_t ny, int32_t nx, const float* v, double sigma, float* out,
+                      void* hip_stream) {
+  if (B < 0 || ny < 1 || nx < 1) return fail(HJG_EINVAL, "need B >= 0 and a grid of at least 1 x 1");
+  if ((int64_t)ny * nx > kMaxCells) return fail(HJG_EUNSUPPORTED, "slices of at most 16,384 cells (128 x 128)");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(HJG_EINVAL, "sigma must be finite and > 0");
+  SmoothTaps T{};
+  T.radius = (int)(4.0 * sigma + 0.5);               // four standard deviations
+  if (2 * T.radius + 1 > kMaxTaps) return fail(HJG_EUNSUPPORTED, "sigma at most 8 cells");
+  if (B == 0) return HJG_OK;
+  if (!v || !out) return fail(HJG_EINVAL, "v and out are required");
+  double wsum = 0.0, w[kMaxTaps];
+  for (int k = -T.radius; k <= T.radius; ++k) wsum += (w[k + T.radius] = std::exp(-0.5 * k * k / (sigma * sigma)));
+  for (int k = 0; k <= 2 * T.radius; ++k) T.w[k] = (float)(w[k] / wsum);
+  smooth_kernel<<<(unsigned)B, kTT, 0, (hipStream_t)hip_stream>>>(ny, nx, v, T, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HJG_EHIP, std::string("smooth_kernel: ") + hipGetErrorString(e));
   return HJG_OK;
 }
 

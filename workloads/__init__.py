@@ -215,3 +215,40 @@ TUBE_MARCH = dict(train_states=16384, N=4096, K=3, width=128, depth=3, epochs=30
                   lr_min=1e-4)
 Q3 = Workload("q3_quadratic_n3", n=3, ham="quadratic", datum="half_sqnorm", nu=0.05, t=1.0, Q=65536, N=65536,
               K=1, box=((-2.0, 2.0),) * 3, tilt=True, sample_mode="crn_step", cfg=8, time_steps=10, T=1.0)
+
+
+# The paper's murmuration study (appendix, simulation setup): 99,996 starlings
+# in six flocks of 16,666, seven pursuers on a ring of radius 1.15 about the
+# flock centre, capture radius 0.6 (union of capture cylinders), delta = 0.18
+# (nu = 0.09), N = 1,600 draws per state, at most seven Picard passes with
+# relative tolerance 1e-5, slices 128 x 128 over [-3.5, 3.5]^2 at altitude 0
+# and heading 0 at 18 times of the horizon [0, 2], smoothed with a Gaussian of
+# 1.5 cells before the topology is read.  Readings (unstated in the paper):
+# speeds v_e = v_p = 1 (its special case), turn rates w_e = w_p = 1, climb
+# bounds g_lo = -0.25, g_hi = 0.25, fresh draws, plain estimator, tube
+# coefficient, birds uniform over the window with altitude in [-0.5, 0.5] and
+# heading in [-pi, pi), one draw stream per flock.
+MURMUR_FLOCKS, MURMUR_BIRDS = 6, 16666
+MURMUR_RING, MURMUR_PURSUERS, MURMUR_WINDOW, MURMUR_SMOOTH = 1.15, 7, 3.5, 1.5
+C8 = Workload("c8_murmuration_n4", n=4, ham="murmuration", ham_p=(1.0, 1.0, 1.0, 1.0, -0.25, 0.25),
+              datum="disc_union", datum_p=(0.6, 7), nu=0.09, t=2.0, Q=MURMUR_FLOCKS * MURMUR_BIRDS, N=1600, K=7,
+              box=((-3.5, 3.5), (-3.5, 3.5), (-0.5, 0.5), (-PI, PI)), tilt=False, sample_mode="fresh", cfg=10,
+              time_steps=18, T=2.0, tube=True)
+
+
+def murmuration_centres() -> np.ndarray:
+    """The pursuers' planar positions, float32 [7, 2]."""
+    a = 2.0 * PI * np.arange(MURMUR_PURSUERS) / MURMUR_PURSUERS
+    return np.stack([MURMUR_RING * np.cos(a), MURMUR_RING * np.sin(a)], 1).astype(np.float32)
+
+
+def starlings() -> np.ndarray:
+    """All birds' relative states, float32 [99,996, 4], flock by flock."""
+    return np.concatenate([queries(C8, Q=MURMUR_BIRDS, trial=f) for f in range(MURMUR_FLOCKS)])
+
+
+def murmuration_window(m: int = 128) -> np.ndarray:
+    """States of the m x m slice over [-3.5, 3.5]^2 at altitude 0 and heading 0, float32 [m*m, 4]."""
+    g = np.linspace(-MURMUR_WINDOW, MURMUR_WINDOW, m)
+    X, Y = np.meshgrid(g, g)
+    return np.stack([X.ravel(), Y.ravel(), np.zeros(m * m), np.zeros(m * m)], 1).astype(np.float32)
