@@ -600,6 +600,63 @@ def rockets_study(ctx, stream):
                     "its own evaluation grid"}
 
 
+def murmuration_study(ctx, stream):
+    """The paper's murmuration study: certify all 99,996 starlings at the end
+    of the horizon (each bird's value read at its own 4D state, per-bird
+    empirical Bernstein margin), and the topology of the zero-sublevel set on
+    the 128 x 128 window at 18 times of the horizon (smoothed by 1.5 cells)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import (ProblemSpec, certify, mc_margin, picard_sweep, smooth_slices, topology,
+                                      topology_events)
+    w = workloads.C8
+    dev = torch.device("cuda:0")
+    cen = torch.from_numpy(workloads.murmuration_centres().ravel()).to(dev)
+    spec = ProblemSpec(datum_aux=cen, **w.problem_fields())
+    birds = torch.from_numpy(np.ascontiguousarray(workloads.starlings().T)).to(dev)
+    win = torch.from_numpy(np.ascontiguousarray(workloads.murmuration_window().T)).to(dev)
+    taus = [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
+    with torch.cuda.stream(stream):
+        picard_sweep(ctx, spec, birds, w.T, w.N, w.K, tol=1e-5, stream=stream)        # records the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pop = picard_sweep(ctx, spec, birds, w.T, w.N, w.K, tol=1e-5, stream=stream)
+        marg = mc_margin(pop.v, pop.c, w.N, 0.05, -float(w.datum_p[0]), ess=pop.ess, stream=stream)
+        lab, cnt = certify(pop.v, 0.0, marg, stream=stream)
+        torch.cuda.synchronize()
+        cert_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        vs = []
+        for j, tau in enumerate(taus):
+            o = picard_sweep(ctx, spec, win, tau, w.N, w.K, tol=1e-5, time_step=j + 1, host_outputs=False,
+                             stream=stream)
+            vs.append(o.v.view(128, 128))
+        sm = smooth_slices(torch.stack(vs).contiguous(), workloads.MURMUR_SMOOTH, stream=stream)
+        nc, b1, chi = topology(sm, stream=stream)
+        torch.cuda.synchronize()
+        topo_s = time.perf_counter() - t0
+    cnt = cnt.cpu().numpy()
+    nc, b1, chi = nc.cpu().numpy(), b1.cpu().numpy(), chi.cpu().numpy()
+    ev = topology_events(chi, b1, nc)
+    names = {1: "vacuole", 2: "cordon", 4: "fragmentation"}
+    v = pop.v.cpu().numpy()
+    return {"workload": f"{w.name}: {w.Q} starlings in {workloads.MURMUR_FLOCKS} flocks, 7 pursuers on a ring of "
+                        f"radius {workloads.MURMUR_RING}, capture radius {w.datum_p[0]}, delta = {2 * w.nu:.2f}, "
+                        f"N = {w.N} common draws per horizon, K <= {w.K} (tol 1e-5), horizon [0, {w.T}]",
+            "population": {"positive_value_fraction": float(np.mean(v > 0)),
+                           "certified_safe_fraction": float(cnt[2] / w.Q), "certified_unsafe": int(cnt[0]),
+                           "undetermined": int(cnt[1]), "picard_iterations": int(pop.iters_done),
+                           "final_relative_residual": float(pop.resid_hist[pop.iters_done - 1]),
+                           "seconds_sweep_margins_labels": cert_s, "paper_positive_fraction": 0.877},
+            "topology": {"tau": taus, "n_comp": nc.tolist(), "beta1": b1.tolist(), "chi": chi.tolist(),
+                         "events": [[names[b] for b in (1, 2, 4) if e & b] for e in ev.tolist()],
+                         "seconds_18_slices": topo_s,
+                         "paper": "hole (beta1 = 1, chi = 0) through tau = 1.18, closing at 1.29; n_comp = 1"},
+            "paper_seconds_whole_study_8_cpu_cores": 429.0}
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -641,6 +698,7 @@ def main():
     ap.add_argument("--no-tube", action="store_true", help="skip the time-marching study")
     ap.add_argument("--no-topology", action="store_true", help="skip the topology-marker study")
     ap.add_argument("--no-rockets", action="store_true", help="skip the two-rocket game study")
+    ap.add_argument("--no-murmuration", action="store_true", help="skip the murmuration study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -734,6 +792,9 @@ def main():
     rstudy = None
     if not args.no_rockets:
         rstudy = rockets_study(ctx, stream)
+    mstudy = None
+    if not args.no_murmuration:
+        mstudy = murmuration_study(ctx, stream)
 
     sec_per_step = (t1 - t0) / args.steps
     pairs_per_step = w.Q * w.N * w.K
@@ -780,6 +841,7 @@ def main():
         "time_marching": tstudy,
         "topology": topo,
         "rockets_game": rstudy,
+        "murmuration": mstudy,
     }
     print(json.dumps(line))
 

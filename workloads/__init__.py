@@ -225,14 +225,16 @@ Q3 = Workload("q3_quadratic_n3", n=3, ham="quadratic", datum="half_sqnorm", nu=0
 # and heading 0 at 18 times of the horizon [0, 2], smoothed with a Gaussian of
 # 1.5 cells before the topology is read.  Readings (unstated in the paper):
 # speeds v_e = v_p = 1 (its special case), turn rates w_e = w_p = 1, climb
-# bounds g_lo = -0.25, g_hi = 0.25, fresh draws, plain estimator, tube
-# coefficient, birds uniform over the window with altitude in [-0.5, 0.5] and
-# heading in [-pi, pi), one draw stream per flock.
+# bounds g_lo = -0.25, g_hi = 0.25, plain estimator, tube coefficient, birds
+# uniform over the window with altitude in [-0.5, 0.5] and heading in
+# [-pi, pi), one query stream per flock; common draws per horizon (with fresh
+# draws per state the sampling error is spatially white and the 1.5-cell
+# smoothing leaves speckle components in the later slices).
 MURMUR_FLOCKS, MURMUR_BIRDS = 6, 16666
 MURMUR_RING, MURMUR_PURSUERS, MURMUR_WINDOW, MURMUR_SMOOTH = 1.15, 7, 3.5, 1.5
 C8 = Workload("c8_murmuration_n4", n=4, ham="murmuration", ham_p=(1.0, 1.0, 1.0, 1.0, -0.25, 0.25),
               datum="disc_union", datum_p=(0.6, 7), nu=0.09, t=2.0, Q=MURMUR_FLOCKS * MURMUR_BIRDS, N=1600, K=7,
-              box=((-3.5, 3.5), (-3.5, 3.5), (-0.5, 0.5), (-PI, PI)), tilt=False, sample_mode="fresh", cfg=10,
+              box=((-3.5, 3.5), (-3.5, 3.5), (-0.5, 0.5), (-PI, PI)), tilt=False, sample_mode="crn_step", cfg=10,
               time_steps=18, T=2.0, tube=True)
 
 
