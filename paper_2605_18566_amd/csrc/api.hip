@@ -46,6 +46,12 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct hjg_ctx {
   int device = 0;
   hipStream_t cap = nullptr;   // stream used only to record graphs
+  // side streams and events of a batched recording: the pair loops of one
+  // Picard level become parallel graph branches
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSide] = {};
   // workspace
   DevBuf pm, pS, pS2, pG, pZ, vprev, cwork, thwork, blockpart, resid, ctrl, table, zbar;
   DevBuf g_cell, g_rank, g_start, g_bsum, g_sorted;   // hash grid of the flock search
@@ -437,6 +443,11 @@ void hjg_ctx_destroy(hjg_ctx* ctx) {
     if (b->p) (void)hipFree(b->p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  for (int j = 0; j < hjg_ctx::kSide; ++j) {
+    if (ctx->side[j]) (void)hipStreamDestroy(ctx->side[j]);
+    if (ctx->join_ev[j]) (void)hipEventDestroy(ctx->join_ev[j]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
 }
@@ -850,6 +861,23 @@ struct SpecKey {
 // so each problem is cut only into splits of about this many samples.
 // Batched sweeps run as persistent launches (resident blocks take work items
 // from a queue) unless HJG_BATCH_PERSISTENT=0 asks for one block per item.
+// The pair loops of one Picard level as parallel branches of the recorded
+// graph (default) unless HJG_BATCH_CONCURRENT=0 asks for one chain.
+bool batched_concurrent() {
+  const char* e = std::getenv("HJG_BATCH_CONCURRENT");
+  return !(e && e[0] == '0');
+}
+
+int ensure_side(hjg_ctx* ctx) {
+  if (ctx->fork_ev) return HJG_OK;
+  for (int j = 0; j < hjg_ctx::kSide; ++j) {
+    HJG_HIP(hipStreamCreateWithFlags(&ctx->side[j], hipStreamNonBlocking));
+    HJG_HIP(hipEventCreateWithFlags(&ctx->join_ev[j], hipEventDisableTiming));
+  }
+  HJG_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  return HJG_OK;
+}
+
 bool batched_persistent() {
   const char* e = std::getenv("HJG_BATCH_PERSISTENT");
   return !(e && e[0] == '0');
@@ -1161,11 +1189,35 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
     HJG_HIP(hipStreamSynchronize(s));
 
     // ---- record the whole uneven multi-problem Picard loop
+    const bool concurrent = batched_concurrent();
+    if (concurrent && (rc = ensure_side(ctx))) return rc;
     HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = persistent ? launch_fill_ints(d_ctr, n_sweeps, 0, ctx->cap) : hipSuccess;
     int sweep_i = 0;
-    for (const Launch& L : launches) {
+    for (size_t li = 0; li < launches.size(); ++li) {
       if (e != hipSuccess) break;
+      const Launch& L = launches[li];
+      size_t lj = li;
+      while (lj < launches.size() && launches[lj].kind == 1) ++lj;
+      if (concurrent && L.kind == 1 && lj - li > 1) {
+        // the level's pair loops: fork from the recording stream onto the side
+        // streams (round robin), join back before the level's finalize
+        const int ns = (int)std::min<size_t>(lj - li, hjg_ctx::kSide);
+        e = hipEventRecord(ctx->fork_ev, ctx->cap);
+        for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->side[j], ctx->fork_ev, 0);
+        for (size_t m = li; m < lj && e == hipSuccess; ++m) {
+          const Launch& M = launches[m];
+          SweepBatch b{d_sa, (const int4*)(d_items + M.off), M.count, persistent ? d_ctr + sweep_i : nullptr};
+          ++sweep_i;
+          e = launch_sweep(sa[M.rep], 0, pl[M.rep].bf16, ctx->side[(m - li) % ns], &b);
+        }
+        for (int j = 0; j < ns && e == hipSuccess; ++j) {
+          e = hipEventRecord(ctx->join_ev[j], ctx->side[j]);
+          if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cap, ctx->join_ev[j], 0);
+        }
+        li = lj - 1;
+        continue;
+      }
       if (L.kind == 0) {
         ItemBatch<InitArgs> b{d_ia, (const int2*)(d_items + L.off), L.count};
         e = launch_init(ia[L.rep], ctx->cap, &b);
