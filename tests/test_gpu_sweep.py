@@ -83,6 +83,10 @@ CASES = {
     "mfma_dubins_n45_ragged": (dict(workloads.C5.problem_fields()), 333, 1000 + 13),
     "mfma_dubins_n48_notilt": (dict(workloads.C5.problem_fields(), n=48, tilt=False), 260, 777),
     "mfma_dubins_n18_cv": (dict(workloads.C5.problem_fields(), n=18, grad_cv=True), 500, 2053),
+    # bfloat16 common tables below n = 16 (vector-ALU loop)
+    "dubins_n3_bf16": (dict(workloads.C2.problem_fields(), sample_bf16=True), 700, 3000 + 11),
+    "dubins_n6_bf16_cv": (dict(workloads.C5.problem_fields(), n=6, grad_cv=True), 513, 1500),
+    "dubins_n15_bf16_notilt": (dict(workloads.C5.problem_fields(), n=15, tilt=False), 400, 2048),
     "mfma_quad_halfsq_n20": (dict(workloads.C1_QUAD.problem_fields(), n=20, sample_mode="crn_step",
                                   sample_bf16=True, tilt=True), 300, 1500),
     "mfma_quad_ball_n16_k3": (dict(workloads.C1.problem_fields(), n=16, datum_p=(3, 1.0), sample_mode="crn_step",
