@@ -464,6 +464,7 @@ int hjg_philox4x32_10(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int6
 }
 
 int hjg_sample_table(hjg_ctx* ctx, const hjg_problem* p, int32_t N, uint32_t step, void* out, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_sample_table");
   g_err.clear();
   int rc = check_common(ctx, p, 0, 1.0, N, step);
   if (rc) return rc;
@@ -478,6 +479,7 @@ int hjg_sample_table(hjg_ctx* ctx, const hjg_problem* p, int32_t N, uint32_t ste
 int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N,
                    uint32_t step, uint32_t iter, const float* c, const float* theta, float* v, float* grad,
                    float* ess, int32_t check_finite, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_value_grad");
   g_err.clear();
   int rc = check_common(ctx, p, Q, t, N, step);
   if (rc) return rc;
@@ -706,6 +708,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
                      double tol, uint32_t step, const float* p0, const float* v0, float* v, float* grad,
                      float* c_out, float* ess, uint8_t* flags, double* resid_hist, int32_t* iters_done,
                      void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_picard_sweep");
   g_err.clear();
   int rc = check_common(ctx, p, Q, t, N, step);
   if (rc) return rc;
@@ -898,6 +901,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
                                         const int32_t* Ns, const int32_t* Ks, const double* ts, double tol,
                                         const float* x_all, float* v_all, float* grad_all, double* resid_hist,
                                         int32_t* iters, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_picard_sweep_batched");
   g_err.clear();
   if (!ctx || !probs || !q_off || !Ns || !Ks || !ts) return fail(HJG_EINVAL, "NULL argument");
   if (P < 1 || P > 65536) return fail(HJG_EINVAL, "P must be in [1, 65536]");
@@ -1269,6 +1273,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
 // ===================================================================== flock
 extern "C" int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const float* box_lo, const float* box_hi,
                             float cell, int32_t k, int32_t* idx, float* nbr_pos, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_knn_grid");
   g_err.clear();
   if (!ctx) return fail(HJG_EINVAL, "NULL context");
   if (!pos || !box_lo || !box_hi) return fail(HJG_EINVAL, "pos, box_lo and box_hi are required");
@@ -1332,6 +1337,7 @@ struct TuneScratch {
 extern "C" int hjg_autotune_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N,
                                   const float* c, const float* theta, int32_t* best_blocks, double* best_ms,
                                   void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_autotune_sweep");
   g_err.clear();
   int rc = check_common(ctx, p, Q, t, N, 0);
   if (rc) return rc;
@@ -1380,6 +1386,7 @@ extern "C" int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* 
                                     const int32_t* Ns, const int32_t* Ks, const double* ts, double tol,
                                     const float* x_all, float* v_all, float* grad_all, int32_t* best_split,
                                     double* best_ms, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_autotune_batched");
   g_err.clear();
   if (!ctx || !best_split || !best_ms) return fail(HJG_EINVAL, "NULL argument");
   HJG_HIP(hipSetDevice(ctx->device));

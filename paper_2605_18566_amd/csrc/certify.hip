@@ -89,6 +89,7 @@ extern "C" {
 
 int hjg_certify(int64_t Q, const float* v, const float* margin, double E, int8_t* label, int64_t* counts,
                 void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_certify");
   if (Q < 0 || Q > ((int64_t)1 << 40)) return fail(HJG_EINVAL, "Q must be in [0, 2^40]");
   if (!(std::isfinite(E) && E >= 0)) return fail(HJG_EINVAL, "E must be finite and >= 0");
   if (Q > 0 && !v) return fail(HJG_EINVAL, "v is required");
@@ -107,6 +108,7 @@ int hjg_certify(int64_t Q, const float* v, const float* margin, double E, int8_t
 
 int hjg_mc_margin(int64_t Q, const float* v, const float* c, const float* ess, int32_t N, double delta_p,
                   double g_min, double g_max, float* margin, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_mc_margin");
   if (Q < 0 || Q > ((int64_t)1 << 40)) return fail(HJG_EINVAL, "Q must be in [0, 2^40]");
   if (N < 1 || (ess && N < 2)) return fail(HJG_EINVAL, "N must be >= 1 (>= 2 with ess)");
   if (!(delta_p > 0 && delta_p < 1)) return fail(HJG_EINVAL, "delta_p must be in (0, 1)");

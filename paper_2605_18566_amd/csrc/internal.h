@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "device.h"
 #include "hjg.h"
 
@@ -20,6 +22,15 @@ HJG_HIDDEN DatumP datum_params(const hjg_problem* p);
 HJG_HIDDEN HamP ham_params(const hjg_problem* p);
 // Philox counter tag of (problem, time step, iteration).
 HJG_HIDDEN uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter);
+
+// A roctx range around one interface call: profilers that record markers
+// (rocprofv3 --marker-trace) attribute the call's kernels to it.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 }  // namespace detail
 }  // namespace hjg

@@ -461,6 +461,7 @@ int hjg_surrogate_load(hjg_ctx* ctx, const char* path, hjg_surrogate** out) {
 
 int hjg_surrogate_predict(hjg_surrogate* s, int64_t Q, const float* x, const float* t, float* v, float* grad,
                           void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_surrogate_predict");
   if (!s) return fail(HJG_EINVAL, "surrogate is NULL");
   if (Q < 0) return fail(HJG_EINVAL, "Q must be >= 0");
   if (Q == 0) return HJG_OK;
@@ -495,6 +496,7 @@ int set_loss_weights(hjg_surrogate* s, double grad_weight, hipStream_t st) {
 
 int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x, const float* t, const float* v,
                             const float* grad, double grad_weight, double* loss, float* grads, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_surrogate_loss_grad");
   if (!s || !loss) return fail(HJG_EINVAL, "NULL argument");
   if (B < 32 || B % 32) return fail(HJG_EINVAL, "B must be a positive multiple of 32");
   if (!x || !t || !v || !grad) return fail(HJG_EINVAL, "x, t, v and grad are required");
@@ -527,6 +529,7 @@ int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x, const f
 
 int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float* t, const float* v,
                         const float* grad, const hjg_train_cfg* cfg, double* loss_hist, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_surrogate_train");
   if (!s || !cfg) return fail(HJG_EINVAL, "NULL argument");
   if (!x || !t || !v || !grad) return fail(HJG_EINVAL, "x, t, v and grad are required");
   const int B = cfg->batch;
@@ -626,6 +629,7 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
 int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, int64_t Q, const float* x, double t,
                         int32_t N_s, int32_t K_s, int32_t N_fb, int32_t K_fb, double tol, uint32_t time_step,
                         float* v, float* grad, uint8_t* fell_back, int64_t* n_fallback, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_surrogate_sweep");
   if (!ctx || !s || !p || !n_fallback) return fail(HJG_EINVAL, "NULL argument");
   if (p->n != s->n) return fail(HJG_EINVAL, "problem dimension differs from the surrogate's");
   if (Q < 0) return fail(HJG_EINVAL, "Q must be >= 0");
@@ -677,6 +681,7 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
                             double t_prev, double dt, int32_t N, int32_t K, double tol, uint32_t time_step,
                             float* v, float* grad, float* c_out, float* ess, double* resid_hist,
                             int32_t* iters_done, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_surrogate_tube_step");
   if (!ctx || !s) return fail(HJG_EINVAL, "context or surrogate is NULL");
   int rc = detail::check_problem(p);
   if (rc) return rc;

@@ -198,6 +198,7 @@ extern "C" {
 
 int hjg_isocontour(int32_t B, int32_t ny, int32_t nx, const float* v, float level, float* seg, int32_t* seg_slice,
                    int64_t max_seg, int64_t* count, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_isocontour");
   if (B < 0 || ny < 1 || nx < 1 || max_seg < 0) return fail(HJG_EINVAL, "need B >= 0, a grid of at least 1 x 1, max_seg >= 0");
   if ((int64_t)B * ny * nx > ((int64_t)1 << 40)) return fail(HJG_EINVAL, "too many grid values");
   if (!count) return fail(HJG_EINVAL, "count is required");
@@ -221,6 +222,7 @@ int hjg_isocontour(int32_t B, int32_t ny, int32_t nx, const float* v, float leve
 
 int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v, int32_t* n_comp, int32_t* beta1, int32_t* chi,
                  void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_topology");
   if (B < 0 || ny < 1 || nx < 1) return fail(HJG_EINVAL, "need B >= 0 and a grid of at least 1 x 1");
   if ((int64_t)ny * nx > kMaxCells) return fail(HJG_EUNSUPPORTED, "slices of at most 16,384 cells (128 x 128)");
   if (B == 0) return HJG_OK;
@@ -233,6 +235,7 @@ int hjg_topology(int32_t B, int32_t ny, int32_t nx, const float* v, int32_t* n_c
 
 int hjg_smooth_slices(int32_t B, int32_t ny, int32_t nx, const float* v, double sigma, float* out,
                       void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_smooth_slices");
   if (B < 0 || ny < 1 || nx < 1) return fail(HJG_EINVAL, "need B >= 0 and a grid of at least 1 x 1");
   if ((int64_t)ny * nx > kMaxCells) return fail(HJG_EUNSUPPORTED, "slices of at most 16,384 cells (128 x 128)");
   if (!(sigma > 0) || !std::isfinite(sigma)) return fail(HJG_EINVAL, "sigma must be finite and > 0");
