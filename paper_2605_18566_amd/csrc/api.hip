@@ -304,12 +304,17 @@ std::string sweep_key(const hjg_problem* p, int64_t Q, int N) {
 // smaller blocks per CU.
 int default_target_blocks(const hjg_problem* p) { return pairs_kernel(p) ? 512 : 2048; }
 
-Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block, int target) {
+// Sample splits for a launch of about `target` blocks.  A split holds at least
+// 16 (n + 3) samples: the float64 merge of one state walks its splits
+// serially, (n + 3) partials each, so many thin splits of few states would
+// make the merge, not the pair loop, the long pole.
+Plan plan_splits(int64_t Q, int N, bool fresh, int queries_per_block, int target, int n) {
   if (const char* e = std::getenv("HJG_TARGET_BLOCKS")) target = std::max(1, std::atoi(e));
   const int64_t qblocks = div_up(Q, queries_per_block);
   const int gran = fresh ? 64 : kBlk;
+  const int64_t min_ns = div_up(16 * (int64_t)(n + 3), gran) * gran;
   int64_t splits = std::max<int64_t>(1, div_up(target, qblocks));
-  splits = std::min<int64_t>(splits, div_up(N, gran));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, div_up(N, std::max<int64_t>(gran, min_ns))));
   int64_t ns = div_up(div_up(N, splits), gran) * gran;
   splits = div_up(N, ns);
   return Plan{(int)splits, (int)ns};
@@ -492,7 +497,7 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   const bool mf = use_mfma(p);
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
   const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p),
-                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second);
+                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second, p->n);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
   const float sigma = (float)std::sqrt(2.0 * p->nu * t);
@@ -725,7 +730,7 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   const bool fresh = p->sample_mode == HJG_S_FRESH;
   const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
   const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p),
-                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second);
+                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second, p->n);
   if ((rc = ensure_partials(ctx, p->n, Q, pl, fresh && p->grad_cv))) return rc;
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
