@@ -142,11 +142,15 @@ constexpr int kXS = kFK + 8;
 template <int K, int LD>
 __device__ __forceinline__ void fused_layer(const __bf16* Hin, const bf16x8_t* wreg, const float* bias, __bf16* Hout,
                                             int f0, int l32, int h) {
+  // accumulators start at the bias of their feature (rows 8(v/4) + 4h + v%4)
+  float4 bv[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) bv[g] = *reinterpret_cast<const float4*>(bias + f0 + 8 * g + 4 * h);
   f32x16_t acc[4];
 #pragma unroll
   for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[st][v] = 0.f;
+    for (int v = 0; v < 16; ++v) acc[st][v] = bv[v / 4][v % 4];
 #pragma unroll
   for (int ks = 0; ks < K / 16; ++ks) {
 #pragma unroll
@@ -155,9 +159,6 @@ __device__ __forceinline__ void fused_layer(const __bf16* Hin, const bf16x8_t* w
       acc[st] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wreg[ks], b, acc[st], 0, 0, 0);
     }
   }
-  float4 bv[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) bv[g] = *reinterpret_cast<const float4*>(bias + f0 + 8 * g + 4 * h);
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
 #pragma unroll
@@ -165,7 +166,7 @@ __device__ __forceinline__ void fused_layer(const __bf16* Hin, const bf16x8_t* w
       bf16x4_t o;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float z = acc[st][4 * g + j] + bv[g][j];
+        const float z = acc[st][4 * g + j];
         o[j] = (__bf16)(z * sigmoid_rcp(z));
       }
       *reinterpret_cast<bf16x4_t*>(Hout + (32 * st + l32) * kHS + f0 + 8 * g + 4 * h) = o;
