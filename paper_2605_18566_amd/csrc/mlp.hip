@@ -14,8 +14,9 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int kTM = 64, kTN = 64, kTK = 32;   // block tile
-constexpr int kLdsK = kTK + 8;                 // padded LDS row (80 bytes, 16-byte aligned)
+constexpr int kTM = 64, kTN = 64, kTK = 32;   // block tile; K ranges are multiples of kTK
+constexpr int kKS = 256;                       // K range staged in LDS per barrier
+constexpr int kLdsK = kKS + 8;                 // padded LDS row (528 bytes, 16-byte aligned)
 
 // logistic function with the hardware reciprocal (shared by every network kernel)
 __device__ __forceinline__ float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
@@ -39,22 +40,36 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row, k offset
-  for (int k0 = kb; k0 < ke; k0 += kTK) {
-    bf16x8 va, vb;
-    if (m0 + lr < g.M) va = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr) * g.lda + k0 + lk);
-    else
+  // Up to kKS of the K range per round: every load of the round is issued
+  // before one barrier (the small training shapes are latency bound), then
+  // the MFMA chain runs in ascending k.
+  const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row, k offset (+ 32 j)
+  const bool arow = m0 + lr < g.M, brow = n0 + lr < g.N;
+  for (int k0 = kb; k0 < ke; k0 += kKS) {
+    const int kc = min(kKS, ke - k0);
+    bf16x8 va[kKS / kTK], vb[kKS / kTK];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) va[e] = (__bf16)0.f;
-    if (n0 + lr < g.N) vb = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)(n0 + lr) * g.ldb + k0 + lk);
-    else
+    for (int j = 0; j < kKS / kTK; ++j) {
+      if (j * kTK >= kc) break;
+      if (arow) va[j] = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr) * g.lda + k0 + j * kTK + lk);
+      else
 #pragma unroll
-      for (int e = 0; e < 8; ++e) vb[e] = (__bf16)0.f;
-    *reinterpret_cast<bf16x8*>(&As[lr][lk]) = va;
-    *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = vb;
+        for (int e = 0; e < 8; ++e) va[j][e] = (__bf16)0.f;
+      if (brow) vb[j] = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)(n0 + lr) * g.ldb + k0 + j * kTK + lk);
+      else
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vb[j][e] = (__bf16)0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kKS / kTK; ++j) {
+      if (j * kTK >= kc) break;
+      *reinterpret_cast<bf16x8*>(&As[lr][j * kTK + lk]) = va[j];
+      *reinterpret_cast<bf16x8*>(&Bs[lr][j * kTK + lk]) = vb[j];
+    }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < kTK; ks += 16) {
+    for (int ks = 0; ks < kKS; ks += 16) {
+      if (ks >= kc) break;
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
       const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);

@@ -179,7 +179,7 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
   SG_HIP(launch_mse_loss((const float*)s->Y.p, (const float*)s->T.p, (const float*)s->lw.p, B, s->nout, s->out_p,
                          (__bf16*)s->dY.p, (__bf16*)s->dYT.p, (double*)s->bl.p, &nb, st));
   SG_HIP(launch_accumulate((const double*)s->bl.p, nb, (double*)s->acc.p, st));
-  const int kps = 512;
+  const int kps = 256;   // batch rows per weight-gradient split (one LDS round each)
   const int splits = (B + kps - 1) / kps;
   if ((rc = grow(s->part, (size_t)splits * s->width * std::max(s->width, s->in_p) * 4 +
                               (size_t)splits * s->out_p * s->width * 4)))
