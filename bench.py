@@ -437,6 +437,60 @@ def pursuit_study(ctx, stream):
                     "in float64); positions uniform over [-100, 100] per coordinate as the paper states"}
 
 
+def _march(ctx, w, cfg, spec, xtr, xev, stream, obstacle=None):
+    """March the workload over its horizons (semigroup form, surrogate as the
+    datum); with an obstacle (ProblemSpec of the avoid set's level) every
+    step's labels and the final values are projected onto the reach-avoid
+    constraint.  Returns the final step at xev, its warm time and the march
+    timings."""
+    import torch
+
+    from paper_2605_18566_amd import Surrogate, TrainConfig, avoid_project, picard_sweep, surrogate_tube_step
+    dt = w.T / w.time_steps
+    M = xtr.shape[1]
+    sur = Surrogate(ctx, w.n, cfg["width"], cfg["depth"], seed=5)
+    tc = dict(epochs=cfg["epochs"], batch=cfg["batch"], lr=cfg["lr"], lr_min=cfg["lr_min"])
+
+    def lift(x, o):
+        if obstacle is not None:
+            avoid_project(obstacle, x, o.v, o.grad, stream=stream)
+        return o
+
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        first = lift(xtr, picard_sweep(ctx, spec, xtr, dt, cfg["N"], cfg["K"], time_step=1, host_outputs=False,
+                                       stream=stream))
+        lx, lt, lv, lg = [xtr], [torch.full((M,), dt, device="cuda:0")], [first.v.clone()], [first.grad.clone()]
+        train_s = step_s = 0.0
+        for j in range(2, w.time_steps + 1):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            sur.train(torch.cat(lx, 1).contiguous(), torch.cat(lt).contiguous(), torch.cat(lv).contiguous(),
+                      torch.cat(lg, 1).contiguous(), TrainConfig(seed=j, **tc), stream=stream)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            o = lift(xtr, surrogate_tube_step(ctx, sur, spec, xtr, (j - 1) * dt, dt, cfg["N"], cfg["K"], time_step=j,
+                                              stream=stream))
+            torch.cuda.synchronize()
+            train_s += b - a
+            step_s += time.perf_counter() - b
+            lx.append(xtr)
+            lt.append(torch.full((M,), j * dt, device="cuda:0"))
+            lv.append(o.v.clone())
+            lg.append(o.grad.clone())
+        march_s = time.perf_counter() - t0
+        # the last step at the evaluation states, timed warm
+        args = (ctx, sur, spec, xev, w.T - dt, dt, cfg["N"], cfg["K"])
+        surrogate_tube_step(*args, time_step=w.time_steps, stream=stream)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ev = lift(xev, surrogate_tube_step(*args, time_step=w.time_steps, stream=stream))
+        torch.cuda.synchronize()
+        ev_s = time.perf_counter() - a
+    sur.close()
+    return ev, ev_s, march_s, train_s, step_s
+
+
 def tube_study(ctx, stream):
     """Time marching with the surrogate as the datum (semigroup form): march
     the n = 3 Dubins tube workload and the exact quadratic case over ten
@@ -446,8 +500,7 @@ def tube_study(ctx, stream):
     import torch
 
     import workloads
-    from paper_2605_18566_amd import (ProblemSpec, Surrogate, TrainConfig, picard_sweep,
-                                      surrogate_tube_step)
+    from paper_2605_18566_amd import ProblemSpec, picard_sweep
     cfg = workloads.TUBE_MARCH
     res = {}
     for w in (workloads.C2, workloads.Q3):
@@ -456,39 +509,8 @@ def tube_study(ctx, stream):
         M = cfg["train_states"]
         xtr = torch.from_numpy(np.ascontiguousarray(workloads.queries(w, Q=M, trial=7).T)).to("cuda:0")
         xev = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to("cuda:0")
-        sur = Surrogate(ctx, w.n, cfg["width"], cfg["depth"], seed=5)
-        tc = dict(epochs=cfg["epochs"], batch=cfg["batch"], lr=cfg["lr"], lr_min=cfg["lr_min"])
-        t0 = time.perf_counter()
+        ev, ev_s, march_s, train_s, step_s = _march(ctx, w, cfg, spec, xtr, xev, stream)
         with torch.cuda.stream(stream):
-            first = picard_sweep(ctx, spec, xtr, dt, cfg["N"], cfg["K"], time_step=1, host_outputs=False,
-                                 stream=stream)
-            lx, lt, lv, lg = [xtr], [torch.full((M,), dt, device="cuda:0")], [first.v.clone()], [first.grad.clone()]
-            train_s = step_s = 0.0
-            for j in range(2, w.time_steps + 1):
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                sur.train(torch.cat(lx, 1).contiguous(), torch.cat(lt).contiguous(), torch.cat(lv).contiguous(),
-                          torch.cat(lg, 1).contiguous(), TrainConfig(seed=j, **tc), stream=stream)
-                torch.cuda.synchronize()
-                b = time.perf_counter()
-                o = surrogate_tube_step(ctx, sur, spec, xtr, (j - 1) * dt, dt, cfg["N"], cfg["K"], time_step=j,
-                                        stream=stream)
-                torch.cuda.synchronize()
-                train_s += b - a
-                step_s += time.perf_counter() - b
-                lx.append(xtr)
-                lt.append(torch.full((M,), j * dt, device="cuda:0"))
-                lv.append(o.v.clone())
-                lg.append(o.grad.clone())
-            march_s = time.perf_counter() - t0
-            # the last step at the evaluation states, timed warm
-            args = (ctx, sur, spec, xev, w.T - dt, dt, cfg["N"], cfg["K"])
-            surrogate_tube_step(*args, time_step=w.time_steps, stream=stream)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            ev = surrogate_tube_step(*args, time_step=w.time_steps, stream=stream)
-            torch.cuda.synchronize()
-            ev_s = time.perf_counter() - a
             direct = picard_sweep(ctx, spec, xev, w.T, w.N, w.K, time_step=w.time_steps, host_outputs=False,
                                   stream=stream)
             torch.cuda.synchronize()
@@ -512,12 +534,77 @@ def tube_study(ctx, stream):
             r["direct_vs_exact_rms"] = float(np.sqrt(np.mean((vd - exact) ** 2)))
             r["exact_rms"] = float(np.sqrt(np.mean(exact ** 2)))
         res[w.name] = r
-        sur.close()
     return {"workload": f"ten horizons t_j = 0.1 j; labels on {cfg['train_states']} training states per step "
                         f"(N = {cfg['N']}, K = {cfg['K']}); network {cfg['depth']} x {cfg['width']} SiLU trained "
                         f"{cfg['epochs']} epochs per step on all labels so far; last step at the workload's states; "
                         "direct = Algorithm 1 at the final horizon from the terminal datum",
             "runs": res}
+
+
+def reach_avoid_study(ctx, stream):
+    """Reach-avoid tube on the n = 3 Dubins workload: the same march as the
+    time-marching study with every step's values projected onto the obstacle
+    constraint of two discs in the relative plane, against the plain tube and
+    against a projection at the final horizon only; then the projection
+    kernel alone at 2^23 states (HBM roofline)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import ProblemSpec, avoid_project
+    w, cfg = workloads.C2, workloads.TUBE_MARCH
+    spec = ProblemSpec(**w.problem_fields())
+    cen = torch.tensor(workloads.AVOID_DISCS, dtype=torch.float32, device="cuda:0")
+    obst = ProblemSpec(n=w.n, datum="disc_union", datum_p=(workloads.AVOID_RADIUS, len(workloads.AVOID_DISCS)),
+                       datum_aux=cen)
+    xtr = torch.from_numpy(np.ascontiguousarray(workloads.queries(w, Q=cfg["train_states"], trial=7).T)).to("cuda:0")
+    xev = torch.from_numpy(np.ascontiguousarray(workloads.queries(w).T)).to("cuda:0")
+    plain, *_ = _march(ctx, w, cfg, spec, xtr, xev, stream)
+    ra, ev_s, march_s, train_s, step_s = _march(ctx, w, cfg, spec, xtr, xev, stream, obstacle=obst)
+    with torch.cuda.stream(stream):
+        final_only_v = plain.v.clone()
+        act = avoid_project(obst, xev, final_only_v, None, want_active=True, stream=stream)
+        torch.cuda.synchronize()
+    x = xev.cpu().numpy().astype(np.float64)
+    c = workloads.AVOID_DISCS
+    lvl = np.min([np.hypot(x[0] - a, x[1] - b) for a, b in c], axis=0) - workloads.AVOID_RADIUS
+    inside = lvl < 0
+    vp, vr, vf = plain.v.cpu().numpy(), ra.v.cpu().numpy(), final_only_v.cpu().numpy()
+    res = {"states": w.Q, "avoid_fraction_of_states": float(np.mean(inside)),
+           "inside_fraction_tube": float(np.mean(vp <= 0)),
+           "inside_fraction_final_projection": float(np.mean(vf <= 0)),
+           "inside_fraction_reach_avoid": float(np.mean(vr <= 0)),
+           "avoid_states_reached_tube": int(np.sum(inside & (vp <= 0))),
+           "avoid_states_reached_reach_avoid": int(np.sum(inside & (vr <= 0))),
+           "reached_only_through_the_obstacle": int(np.sum((vf <= 0) & (vr > 0))),
+           "final_projection_active": float(act.float().mean().item()),
+           "march_seconds": march_s, "training_seconds": train_s, "label_step_seconds": step_s,
+           "last_step_seconds": ev_s}
+    # the projection kernel alone, 2^23 states, fresh values for every timed call
+    Q, reps = 1 << 23, 8
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    xb = (torch.rand((w.n, Q), generator=g, device="cuda:0") * 6 - 3).contiguous()
+    vs = [(torch.rand(Q, generator=g, device="cuda:0") * 4 - 2) for _ in range(reps + 1)]
+    gs = [torch.zeros((w.n, Q), device="cuda:0") for _ in range(reps + 1)]
+    flags = []
+    with torch.cuda.stream(stream):
+        avoid_project(obst, xb, vs[reps], gs[reps], want_active=True, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            flags.append(avoid_project(obst, xb, vs[i], gs[i], want_active=True, stream=stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    active = float(torch.stack([f.float().mean() for f in flags]).mean().item())
+    bytes_per = Q * (4 * w.n + 4 + 1) + active * Q * 4 * (w.n + 1)
+    res["projection_kernel"] = {"states": Q, "active_fraction": active, "us_per_launch": ms * 1e3,
+                                "algorithmic_bytes": bytes_per, "hbm_gbs": bytes_per / (ms * 1e-3) / 1e9,
+                                "hbm_frac": bytes_per / (ms * 1e-3) / 8e12}
+    return {"workload": f"{w.name} marched over ten horizons as in the time-marching study; avoid set = union of "
+                        f"discs of radius {workloads.AVOID_RADIUS} about {workloads.AVOID_DISCS} in the relative "
+                        "plane (heading free); projection after every step (splitting form)", "result": res}
 
 
 def topology_study(ctx, stream):
@@ -697,6 +784,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the C1/C2 small-configuration study")
     ap.add_argument("--no-tube", action="store_true", help="skip the time-marching study")
     ap.add_argument("--no-topology", action="store_true", help="skip the topology-marker study")
+    ap.add_argument("--no-reach-avoid", action="store_true", help="skip the reach-avoid tube study")
     ap.add_argument("--no-rockets", action="store_true", help="skip the two-rocket game study")
     ap.add_argument("--no-murmuration", action="store_true", help="skip the murmuration study")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
@@ -786,6 +874,9 @@ def main():
     tstudy = None
     if not args.no_tube:
         tstudy = tube_study(ctx, stream)
+    rastudy = None
+    if not args.no_reach_avoid:
+        rastudy = reach_avoid_study(ctx, stream)
     topo = None
     if not args.no_topology:
         topo = topology_study(ctx, stream)
@@ -839,6 +930,7 @@ def main():
         "pursuit_game": pstudy,
         "small_configs": sstudy,
         "time_marching": tstudy,
+        "reach_avoid": rastudy,
         "topology": topo,
         "rockets_game": rstudy,
         "murmuration": mstudy,

@@ -425,6 +425,32 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
 
 /*
  * ------------------------------------------------------------------------
+ * Reach-avoid tube (the viscous reach-avoid variational inequality
+ * HJI-RCBRAT-Visc, Section "Relations to Backward Reachable Sets/Tubes" and
+ * the reach-avoid tube of the appendix): states of an avoid set
+ * A = {l_A <= 0} must never count as reached.  In splitting form each time
+ * step is the ordinary step (Algorithm 1, or hjg_surrogate_tube_step)
+ * followed by the obstacle projection
+ *   v <- max(v, -l_A(x)),   grad <- -D l_A(x) where -l_A(x) > v,
+ * so every state of A keeps a value >= -l_A > 0 and no time step can bring
+ * it below zero.  Marching then trains the next step's datum on the projected
+ * labels.
+ * ------------------------------------------------------------------------
+ */
+/* Obstacle projection in place.  obstacle: a problem record that passes the
+ * usual checks, of which only n and the datum fields (datum, datum_p,
+ * datum_aux) are used: l_A is that datum (same kinks and tie rules as the
+ * sweep's; knn_balls aux is indexed by the state index q < Q).  x device
+ * [n][Q] (dimension-major, float32); v device [Q] in/out; grad device [n][Q]
+ * in/out or NULL (then only v changes); active device uint8 [Q] out or NULL:
+ * 1 where the projection replaced the value (strictly -l_A(x) > v in float32;
+ * a NaN value is kept).  Q = 0 is a no-op.  Asynchronous on hip_stream.
+ * Errors: HJG_EINVAL (NULL pointers with Q > 0, Q < 0, problem checks). */
+int hjg_avoid_project(const hjg_problem* obstacle, int64_t Q, const float* x, float* v, float* grad,
+                      uint8_t* active, void* hip_stream);
+
+/*
+ * ------------------------------------------------------------------------
  * Conservative safety certification (corollary "conservative safety
  * certification" of the total-error theorem).  A state is unsafe iff its
  * value is <= 0.  With a total error budget E the estimate certifies a state

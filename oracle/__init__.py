@@ -38,6 +38,10 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   topology.markers / events      : hand-built slices of plain topology (discs,
                                    rings, holes open to the border, diagonal
                                    contact) and a hand-made event sequence
+  avoid.project                  : the reach-avoid property (no avoid-set state
+                                   reached), lattice property of the maximum,
+                                   brute-force obstacle level, projected
+                                   gradient vs central differences, idempotence
   contour.segments               : exact on linear fields, circle length and
                                    radius, the two saddle cells by hand
   model.hamiltonian (Dubins,     : brute-force max-min over control grids

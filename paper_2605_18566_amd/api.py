@@ -512,6 +512,27 @@ def certify(v: torch.Tensor, E: float = 0.0, margin: Optional[torch.Tensor] = No
     return label, counts
 
 
+# ------------------------------------------------------------------ reach-avoid
+def avoid_project(obstacle: ProblemSpec, x: torch.Tensor, v: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                  want_active: bool = False, stream=None) -> Optional[torch.Tensor]:
+    """Obstacle projection of the reach-avoid tube, in place: v <- max(v, -l_A(x)) and grad <- -D l_A(x) where
+    the obstacle wins; l_A is the datum of `obstacle` (only n and its datum fields are used).  x [n, Q], v [Q],
+    grad [n, Q] float32 device tensors.  Returns the uint8 flags of the replaced states when asked."""
+    _require_cuda(x, "x")
+    _require_cuda(v, "v")
+    if grad is not None:
+        _require_cuda(grad, "grad")
+        if grad.shape != x.shape:
+            raise ValueError("grad must have the shape of x")
+    if x.dim() != 2 or x.shape[0] != obstacle.n or v.numel() != x.shape[1]:
+        raise ValueError("need x [n, Q] and v [Q] with n = obstacle.n")
+    active = torch.empty(v.numel(), dtype=torch.uint8, device=v.device) if want_active else None
+    p = obstacle.to_c()
+    check(_lib.lib().hjg_avoid_project(C.byref(p), v.numel(), _ptr(x), _ptr(v), _ptr(grad), _ptr(active),
+                                       _stream(stream)))
+    return active
+
+
 # ------------------------------------------------------------------ topology
 def topology(v: torch.Tensor, stream=None):
     """Markers of {v <= 0} on slices v [B, ny, nx] (or [ny, nx]): (n_comp, beta1, chi) int32 tensors [B]."""

@@ -213,6 +213,10 @@ def c3_fields(bp: BatchProblem) -> dict:
 # last step evaluated at the workload's 65,536 states.
 TUBE_MARCH = dict(train_states=16384, N=4096, K=3, width=128, depth=3, epochs=30, batch=1024, lr=2e-3,
                   lr_min=1e-4)
+# Reach-avoid variant of the n = 3 Dubins tube: the avoid set is the union of
+# two discs of radius 0.6 in the relative plane (the heading is free).
+AVOID_DISCS = ((1.5, 0.0), (-1.0, -1.2))
+AVOID_RADIUS = 0.6
 Q3 = Workload("q3_quadratic_n3", n=3, ham="quadratic", datum="half_sqnorm", nu=0.05, t=1.0, Q=65536, N=65536,
               K=1, box=((-2.0, 2.0),) * 3, tilt=True, sample_mode="crn_step", cfg=8, time_steps=10, T=1.0)
 
