@@ -32,22 +32,32 @@ struct GemmArgs {
   int ldobT;
   const float* zprev;  // EPI_BWD_DX: [M][ldz]
   int ldz;
+  float* pbias;        // EPI_DW: row sums of A over each split's K range, [splits][M], or nullptr
 };
 
 hipError_t launch_gemm(int epi, const GemmArgs& a, int splits, hipStream_t s);
-// dst[m][n] (+)= sum_z part[z][m][n] for m < M, n < N (row stride ld)
+// dst[m][n] = sum_z part[z][m][n] for m < M, n < N (row stride ld); with pbias
+// also bdst[m] = sum_z pbias[z][m]
 hipError_t launch_sum_splits(const float* part, int splits, int M, int N, int ld, float* dst, int ldd,
-                             hipStream_t s);
-// out[r] = sum_c inT[r][c] for r < R, c < C (bfloat16 rows of stride ld)
-hipError_t launch_row_sums(const __bf16* inT, int R, int C, int ld, float* out, hipStream_t s);
+                             const float* pbias, float* bdst, hipStream_t s);
 // dY = 2 w_j (Y - T) / B (bfloat16 and transposed); loss partial sums per block (float64)
 hipError_t launch_mse_loss(const float* Y, const float* T, const float* w, int B, int cols, int ld, __bf16* dY,
                            __bf16* dYT, double* block_loss, int* nblocks, hipStream_t s);
 // AdamW whose learning rate and bias corrections come from device step
 // counters ctr = {global step, optimizer steps done, batch of the epoch}.
+// With a layer table, every updated weight is also written to its layer's
+// bfloat16 copies (plain [fout][fin] and transposed).
+constexpr int kMaxLayers = 17;
+struct LayerTab {
+  int L;
+  int64_t woff[kMaxLayers];   // first weight of layer l in the flat parameter vector
+  int fin[kMaxLayers], fout[kMaxLayers];
+  __bf16* Wb[kMaxLayers];
+  __bf16* WbT[kMaxLayers];
+};
 hipError_t launch_adamw_sched(float* w, const float* g, float* m, float* v, int64_t count, const int64_t* ctr,
                               double lr_max, double lr_min, int64_t total, float beta1, float beta2, float eps,
-                              float wd, hipStream_t s);
+                              float wd, const LayerTab* tab, hipStream_t s);
 // ctr[0..2] += 1 (one thread)
 hipError_t launch_advance_counters(int64_t* ctr, hipStream_t s);
 hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int64_t count, float lr, float beta1,

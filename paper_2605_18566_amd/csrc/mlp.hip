@@ -45,6 +45,10 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   // the MFMA chain runs in ascending k.
   const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row, k offset (+ 32 j)
   const bool arow = m0 + lr < g.M, brow = n0 + lr < g.N;
+  // EPI_DW with pbias: the first column of blocks also sums its A rows
+  // (row lr, k offsets lk + 32 j) for the bias gradient
+  const bool rowsum = EPI == EPI_DW && g.pbias && blockIdx.x == 0;
+  float bsum = 0.f;
   for (int k0 = kb; k0 < ke; k0 += kKS) {
     const int kc = min(kKS, ke - k0);
     bf16x8 va[kKS / kTK], vb[kKS / kTK];
@@ -67,6 +71,15 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       *reinterpret_cast<bf16x8*>(&Bs[lr][j * kTK + lk]) = vb[j];
     }
     __syncthreads();
+    if (rowsum) {
+#pragma unroll
+      for (int j = 0; j < kKS / kTK; ++j) {
+        if (j * kTK >= kc) break;
+        const bf16x8 r = *reinterpret_cast<const bf16x8*>(&As[lr][j * kTK + lk]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += (float)r[e];
+      }
+    }
 #pragma unroll
     for (int ks = 0; ks < kKS; ks += 16) {
       if (ks >= kc) break;
@@ -75,6 +88,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
+  }
+  if (rowsum) {
+    bsum += __shfl_xor(bsum, 1);
+    bsum += __shfl_xor(bsum, 2);
+    if ((tid & 3) == 0 && arow) g.pbias[(int64_t)blockIdx.z * g.M + m0 + lr] = bsum;
   }
   const int n = n0 + wn * 32 + (lane & 31);
   // transposed bf16 copies go through an LDS tile so their stores are
@@ -122,27 +140,20 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 }
 
 __global__ __launch_bounds__(256) void sum_splits_kernel(const float* part, int splits, int M, int N, int ld,
-                                                         float* dst, int ldd) {
+                                                         float* dst, int ldd, const float* pbias, float* bdst) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)M * N) return;
-  const int m = (int)(i / N), n = (int)(i % N);
-  float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[((int64_t)z * M + m) * ld + n];
-  dst[(int64_t)m * ldd + n] = s;
-}
-
-__global__ __launch_bounds__(256) void row_sums_kernel(const __bf16* inT, int C, int ld, float* out) {
-  const int r = blockIdx.x;
-  float s = 0.f;
-  for (int c = threadIdx.x; c < C; c += 256) s += (float)inT[(int64_t)r * ld + c];
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  const int64_t MN = (int64_t)M * N;
+  if (i < MN) {
+    const int m = (int)(i / N), n = (int)(i % N);
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[((int64_t)z * M + m) * ld + n];
+    dst[(int64_t)m * ldd + n] = s;
+  } else if (pbias && i < MN + M) {
+    const int m = (int)(i - MN);
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += pbias[(int64_t)z * M + m];
+    bdst[m] = s;
   }
-  if (threadIdx.x == 0) out[r] = red[0];
 }
 
 __global__ __launch_bounds__(256) void mse_kernel(const float* Y, const float* T, const float* w, int B, int cols,
@@ -187,21 +198,40 @@ __global__ __launch_bounds__(256) void adamw_kernel(float* w, const float* g, fl
 // AdamW with the step's learning rate and bias corrections formed on the
 // device from the step counters ctr = {global step k, optimizer steps done,
 // batch of the epoch}: cosine schedule lr_min + (lr - lr_min)(1 + cos(pi k/total))/2.
+// The schedule (one cosine and two powers in float64) is formed once per
+// block.  With tab, each weight (not bias) also refreshes its bfloat16 copies.
 __global__ __launch_bounds__(256) void adamw_sched_kernel(float* w, const float* g, float* m, float* v, int64_t count,
                                                           const int64_t* ctr, double lr_max, double lr_min,
-                                                          int64_t total, float b1, float b2, float eps, float wd) {
+                                                          int64_t total, float b1, float b2, float eps, float wd,
+                                                          LayerTab tab) {
+  __shared__ float sched[3];
+  if (threadIdx.x == 0) {
+    const double k = (double)ctr[0], step = (double)(ctr[1] + 1);
+    sched[0] = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * k / (double)total)));
+    sched[1] = (float)(1.0 - pow((double)b1, step));
+    sched[2] = (float)(1.0 - pow((double)b2, step));
+  }
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
-  const double k = (double)ctr[0], step = (double)(ctr[1] + 1);
-  const float lr = (float)(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + cos(M_PI * k / (double)total)));
-  const float bc1 = (float)(1.0 - pow((double)b1, step)), bc2 = (float)(1.0 - pow((double)b2, step));
+  const float lr = sched[0], bc1 = sched[1], bc2 = sched[2];
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
   const float mh = mi / bc1, vh = vi / bc2;
-  w[i] = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+  const float wi = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+  w[i] = wi;
+  for (int l = 0; l < tab.L; ++l) {
+    const int64_t e = i - tab.woff[l];
+    if (e >= 0 && e < (int64_t)tab.fin[l] * tab.fout[l]) {
+      const int r = (int)(e / tab.fin[l]), c = (int)(e % tab.fin[l]);
+      const __bf16 b = (__bf16)wi;
+      tab.Wb[l][e] = b;
+      tab.WbT[l][(int64_t)c * tab.fout[l] + r] = b;
+    }
+  }
 }
 
 __global__ void advance_counters_kernel(int64_t* ctr) {
@@ -393,13 +423,10 @@ hipError_t launch_gemm(int epi, const GemmArgs& a, int splits, hipStream_t s) {
 }
 
 hipError_t launch_sum_splits(const float* part, int splits, int M, int N, int ld, float* dst, int ldd,
-                             hipStream_t s) {
-  sum_splits_kernel<<<nblk((int64_t)M * N), 256, 0, s>>>(part, splits, M, N, ld, dst, ldd);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_sums(const __bf16* inT, int R, int C, int ld, float* out, hipStream_t s) {
-  row_sums_kernel<<<R, 256, 0, s>>>(inT, C, ld, out);
+                             const float* pbias, float* bdst, hipStream_t s) {
+  if (pbias && !bdst) return hipErrorInvalidValue;
+  sum_splits_kernel<<<nblk((int64_t)M * N + (pbias ? M : 0)), 256, 0, s>>>(part, splits, M, N, ld, dst, ldd, pbias,
+                                                                           bdst);
   return hipGetLastError();
 }
 
@@ -419,8 +446,14 @@ hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int64_t co
 
 hipError_t launch_adamw_sched(float* w, const float* g, float* m, float* v, int64_t count, const int64_t* ctr,
                               double lr_max, double lr_min, int64_t total, float beta1, float beta2, float eps,
-                              float wd, hipStream_t s) {
-  adamw_sched_kernel<<<nblk(count), 256, 0, s>>>(w, g, m, v, count, ctr, lr_max, lr_min, total, beta1, beta2, eps, wd);
+                              float wd, const LayerTab* tab, hipStream_t s) {
+  LayerTab t{};
+  if (tab) {
+    if (tab->L < 0 || tab->L > kMaxLayers) return hipErrorInvalidValue;
+    t = *tab;
+  }
+  adamw_sched_kernel<<<nblk(count), 256, 0, s>>>(w, g, m, v, count, ctr, lr_max, lr_min, total, beta1, beta2, eps, wd,
+                                                 t);
   return hipGetLastError();
 }
 

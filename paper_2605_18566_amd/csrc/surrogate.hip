@@ -181,8 +181,10 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
   SG_HIP(launch_accumulate((const double*)s->bl.p, nb, (double*)s->acc.p, st));
   const int kps = 256;   // batch rows per weight-gradient split (one LDS round each)
   const int splits = (B + kps - 1) / kps;
+  // weight-gradient partials [splits][M][N], then the bias partials [splits][M]
   if ((rc = grow(s->part, (size_t)splits * s->width * std::max(s->width, s->in_p) * 4 +
-                              (size_t)splits * s->out_p * s->width * 4)))
+                              (size_t)splits * s->out_p * s->width * 4 +
+                              (size_t)splits * std::max(s->width, s->out_p) * 4)))
     return rc;
   float* g = (float*)s->g.p;
   // output layer
@@ -199,10 +201,10 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
     a.k_per_split = kps;
     a.outf = (float*)s->part.p;
     a.ldo = s->width;
+    a.pbias = (float*)s->part.p + (size_t)splits * s->out_p * s->width;
     SG_HIP(launch_gemm(EPI_DW, a, splits, st));
     SG_HIP(launch_sum_splits((const float*)s->part.p, splits, s->out_p, s->width, s->width, g + s->woff[l], s->width,
-                             st));
-    SG_HIP(launch_row_sums((const __bf16*)s->dYT.p, s->out_p, B, B, g + s->boff[l], st));
+                             a.pbias, g + s->boff[l], st));
     GemmArgs d{};
     d.A = (const __bf16*)s->dY.p;
     d.lda = s->out_p;
@@ -233,10 +235,10 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
     a.k_per_split = kps;
     a.outf = (float*)s->part.p;
     a.ldo = s->fin[l];
+    a.pbias = (float*)s->part.p + (size_t)splits * s->width * s->fin[l];
     SG_HIP(launch_gemm(EPI_DW, a, splits, st));
     SG_HIP(launch_sum_splits((const float*)s->part.p, splits, s->width, s->fin[l], s->fin[l], g + s->woff[l],
-                             s->fin[l], st));
-    SG_HIP(launch_row_sums((const __bf16*)s->dZT[cur].p, s->width, B, B, g + s->boff[l], st));
+                             s->fin[l], a.pbias, g + s->boff[l], st));
     if (l > 0) {
       GemmArgs d{};
       d.A = (const __bf16*)s->dZ[cur].p;
@@ -559,9 +561,19 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
   if ((rc = grow(s->ctr, 3 * sizeof(int64_t)))) return rc;
   int64_t* ctr = (int64_t*)s->ctr.p;
   // One training step: batch gather, forward, backward, AdamW (learning rate
-  // and bias corrections from the device counters), bf16 weight refresh,
-  // counter advance.  The first step runs directly (it also sizes every
-  // workspace); the rest replay it as a recorded graph.
+  // and bias corrections from the device counters) with the bf16 weight
+  // refresh, counter advance.  The first step runs directly (it also sizes
+  // every workspace); the rest replay it as a recorded graph.
+  if (s->L > kMaxLayers) return fail(HJG_EINVAL, "too many layers for the fused optimizer step");
+  LayerTab tab{};
+  tab.L = s->L;
+  for (int l = 0; l < s->L; ++l) {
+    tab.woff[l] = s->woff[l];
+    tab.fin[l] = s->fin[l];
+    tab.fout[l] = s->fout[l];
+    tab.Wb[l] = (__bf16*)s->Wb[l].p;
+    tab.WbT[l] = (__bf16*)s->WbT[l].p;
+  }
   auto train_step = [&](hipStream_t q) -> int {
     int r;
     SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, B, s->in_p,
@@ -570,8 +582,7 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
     if ((r = backward(s, B, q))) return r;
     SG_HIP(launch_adamw_sched((float*)s->w.p, (const float*)s->g.p, (float*)s->m.p, (float*)s->v.p, s->P, ctr,
                               cfg->lr, cfg->lr_min, total, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps,
-                              (float)cfg->weight_decay, q));
-    if ((r = refresh_bf16(s, q))) return r;
+                              (float)cfg->weight_decay, &tab, q));
     SG_HIP(launch_advance_counters(ctr, q));
     return HJG_OK;
   };
