@@ -148,12 +148,43 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
   if (active) {
     const int64_t Q = F.Q;
     double M = -INFINITY;
+#pragma unroll 8
     for (int s = 0; s < F.splits; ++s) M = fmax(M, (double)F.part.m[(int64_t)s * Q + q]);
-    double S = 0.0, S2 = 0.0;
+    // One pass over the splits: each split's rescale factor is formed once
+    // and applied to S, S2 and every gradient sum (each sum still runs over
+    // the splits in ascending order).  Every per-dimension load is issued
+    // without a branch (rows d >= n re-read row n - 1 and are never used), so
+    // a split's loads are in flight together instead of one latency each.
+    // Fresh draws (the only user of the per-query z sums) exist for n <= 16.
+    constexpr bool kZ = NM <= 16;
+    const bool zsum = kZ && F.cv && F.fresh;
+    double S = 0.0, S2 = 0.0, G[NM], Z[kZ ? NM : 1];
+#pragma unroll
+    for (int d = 0; d < NM; ++d) G[d] = 0.0;
+#pragma unroll
+    for (int d = 0; d < (kZ ? NM : 1); ++d) Z[d] = 0.0;
     for (int s = 0; s < F.splits; ++s) {
       const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
       S += F.part.S[(int64_t)s * Q + q] * f;
       S2 += F.part.S2[(int64_t)s * Q + q] * f * f;
+#pragma unroll
+      for (int d = 0; d < NM; ++d) {
+        const int64_t idx = ((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q;
+        G[d] += (double)F.part.G[idx] * f;
+      }
+      if constexpr (kZ) {
+        if (zsum) {
+#pragma unroll
+          for (int d = 0; d < NM; ++d) Z[d] += (double)F.part.Z[((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q];
+        }
+      }
+    }
+    float xv[NM], thv[NM];
+#pragma unroll
+    for (int d = 0; d < NM; ++d) {
+      const int64_t idx = (int64_t)(d < F.n ? d : F.n - 1) * Q + q;
+      xv[d] = F.x[idx];
+      thv[d] = F.theta ? F.theta[idx] : 0.f;
     }
     const double c = (double)F.c[q];
     const double sg = (double)F.sigma;
@@ -164,20 +195,13 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
       xq[d] = 0.f;
       pg[d] = 0.f;
       if (d < F.n) {
-        double G = 0.0, Z = 0.0;
-        for (int s = 0; s < F.splits; ++s) {
-          const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
-          const int64_t idx = ((int64_t)s * F.n + d) * Q + q;
-          G += (double)F.part.G[idx] * f;
-          if (F.cv && F.fresh) Z += (double)F.part.Z[idx];
-        }
-        double gbar = G / S;
-        if (F.cv) gbar -= F.fresh ? Z / (double)F.N : F.zbar_tab[d];
-        const double th = F.theta ? (double)F.theta[(int64_t)d * Q + q] : 0.0;
+        double gbar = G[d] / S;
+        if (F.cv) gbar -= zsum ? Z[kZ ? d : 0] / (double)F.N : F.zbar_tab[d];
+        const double th = (double)thv[d];
         const double gr = -(th + sg * gbar) / (c * sg * sg);
         pg[d] = (float)gr;
         F.grad[(int64_t)d * Q + q] = pg[d];
-        xq[d] = F.x[(int64_t)d * Q + q];
+        xq[d] = xv[d];
       }
     }
     const float vf = (float)v;
