@@ -74,14 +74,15 @@ def test_forward_matches_oracle(ctx, n, width, depth):
     sur.close()
 
 
-@pytest.mark.parametrize("n,width,depth", [(8, 64, 2), (45, 256, 4)])
-def test_loss_and_gradients_match_oracle(ctx, n, width, depth):
+# B = 4,096 at width 256 takes the 64-row GEMM tiles (and 16 weight-gradient
+# splits with their bias sums); the smaller batches take the 32-row tiles.
+@pytest.mark.parametrize("n,width,depth,B", [(8, 64, 2, 256), (45, 256, 4, 256), (45, 256, 4, 4096)])
+def test_loss_and_gradients_match_oracle(ctx, n, width, depth, B):
     from paper_2605_18566_amd import Surrogate
     sizes, layers, norm = random_net(n, width, depth, 3)
     sur = Surrogate(ctx, n, width, depth)
     sur.set_params(flat_from_layers(layers), norm)
     rng = np.random.default_rng(4)
-    B = 256
     x = rng.normal(0, 1.5, (n, B)).astype(np.float32)
     t = rng.uniform(0.1, 1.0, B).astype(np.float32)
     v = rng.normal(0, 1, B).astype(np.float32)
@@ -98,6 +99,38 @@ def test_loss_and_gradients_match_oracle(ctx, n, width, depth):
     for (gW, gb), (rW, rb) in zip(got, ref_grads):
         assert np.linalg.norm(gW - rW) <= 3e-2 * np.linalg.norm(rW)
         assert np.linalg.norm(gb - rb) <= 3e-2 * np.linalg.norm(rb) + 1e-7
+    sur.close()
+
+
+def test_weight_copies_follow_training(ctx):
+    """The optimizer step also refreshes the bfloat16 weight copies the
+    forward pass reads: after training, predictions equal the oracle's forward
+    pass with the trained parameters (stale copies would miss 16 AdamW steps)."""
+    from paper_2605_18566_amd import Surrogate, TrainConfig
+    n, width, depth, M = 8, 64, 2, 4096
+    rng = np.random.default_rng(21)
+    x = rng.normal(0, 1.5, (n, M)).astype(np.float32)
+    t = rng.uniform(0.1, 1.0, M).astype(np.float32)
+    v = rng.normal(0, 1, M).astype(np.float32)
+    g = rng.normal(0, 1, (n, M)).astype(np.float32)
+    sur = Surrogate(ctx, n, width, depth, seed=2)
+    p0, _ = sur.get_params()
+    sur.train(to_dev(x), to_dev(t), to_dev(v), to_dev(g), TrainConfig(epochs=2, batch=512, lr=1e-2, seed=1))
+    p, norm = sur.get_params()
+    assert np.linalg.norm(p - p0) > 0.05 * np.linalg.norm(p0)
+    sizes = [n + 1] + [width] * depth + [n + 1]
+    layers = layers_from_flat(p, sizes)
+    Q = 1000
+    xq = rng.normal(0, 1.5, (n, Q)).astype(np.float32)
+    tq = rng.uniform(0.1, 1.0, Q).astype(np.float32)
+    vp, gp = sur.predict(to_dev(xq), to_dev(tq))
+    torch.cuda.synchronize()
+    lw = [(bf16(W), b) for W, b in layers]
+    xt = np.concatenate([xq.T, tq[:, None]], 1).astype(np.float64)
+    Y, _ = mlp.forward(lw, bf16((xt - norm[0]) / norm[1]))
+    out = Y * norm[3] + norm[2]
+    assert np.linalg.norm(vp.cpu().numpy() - out[:, 0]) <= 1e-2 * np.linalg.norm(out[:, 0])
+    assert np.linalg.norm(gp.cpu().numpy().T - out[:, 1:]) <= 1e-2 * np.linalg.norm(out[:, 1:])
     sur.close()
 
 
