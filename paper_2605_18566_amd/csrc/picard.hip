@@ -140,16 +140,17 @@ __global__ __launch_bounds__(kThreads) void init_batched_kernel(const InitArgs* 
 //   ESS = S^2 / S2,
 // and, inside the Picard loop, the residual terms, the per-query flag and the
 // next coefficient and shift from p = Dv.
-template <int NM>
+// MERGE: several sample splits, merged in one pass (below); otherwise one
+// split, whose sums need no rescaling and whose per-dimension loads go one at
+// a time — the low register count keeps enough waves resident at large Q.
+// Both forms give the same bits for one split (the rescale factor is exactly 1).
+template <int NM, bool MERGE>
 __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qblock) {
   const int64_t q = qblock * kThreads + threadIdx.x;
   const bool active = q < F.Q;
   double dv2 = 0.0, vp2 = 0.0;
   if (active) {
     const int64_t Q = F.Q;
-    double M = -INFINITY;
-#pragma unroll 8
-    for (int s = 0; s < F.splits; ++s) M = fmax(M, (double)F.part.m[(int64_t)s * Q + q]);
     // One pass over the splits: each split's rescale factor is formed once
     // and applied to S, S2 and every gradient sum (each sum still runs over
     // the splits in ascending order).  Every per-dimension load is issued
@@ -157,34 +158,44 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
     // a split's loads are in flight together instead of one latency each.
     // Fresh draws (the only user of the per-query z sums) exist for n <= 16.
     constexpr bool kZ = NM <= 16;
+    constexpr int NG = MERGE ? NM : 1;
     const bool zsum = kZ && F.cv && F.fresh;
-    double S = 0.0, S2 = 0.0, G[NM], Z[kZ ? NM : 1];
+    double M, S = 0.0, S2 = 0.0, G[NG], Z[MERGE && kZ ? NM : 1];
+    float xv[NG], thv[NG];
+    if constexpr (MERGE) {
+      M = -INFINITY;
+#pragma unroll 8
+      for (int s = 0; s < F.splits; ++s) M = fmax(M, (double)F.part.m[(int64_t)s * Q + q]);
 #pragma unroll
-    for (int d = 0; d < NM; ++d) G[d] = 0.0;
+      for (int d = 0; d < NM; ++d) G[d] = 0.0;
 #pragma unroll
-    for (int d = 0; d < (kZ ? NM : 1); ++d) Z[d] = 0.0;
-    for (int s = 0; s < F.splits; ++s) {
-      const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
-      S += F.part.S[(int64_t)s * Q + q] * f;
-      S2 += F.part.S2[(int64_t)s * Q + q] * f * f;
+      for (int d = 0; d < (kZ ? NM : 1); ++d) Z[d] = 0.0;
+      for (int s = 0; s < F.splits; ++s) {
+        const double f = exp2((double)F.part.m[(int64_t)s * Q + q] - M);
+        S += F.part.S[(int64_t)s * Q + q] * f;
+        S2 += F.part.S2[(int64_t)s * Q + q] * f * f;
 #pragma unroll
-      for (int d = 0; d < NM; ++d) {
-        const int64_t idx = ((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q;
-        G[d] += (double)F.part.G[idx] * f;
-      }
-      if constexpr (kZ) {
-        if (zsum) {
+        for (int d = 0; d < NM; ++d) {
+          const int64_t idx = ((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q;
+          G[d] += (double)F.part.G[idx] * f;
+        }
+        if constexpr (kZ) {
+          if (zsum) {
 #pragma unroll
-          for (int d = 0; d < NM; ++d) Z[d] += (double)F.part.Z[((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q];
+            for (int d = 0; d < NM; ++d) Z[d] += (double)F.part.Z[((int64_t)s * F.n + (d < F.n ? d : F.n - 1)) * Q + q];
+          }
         }
       }
-    }
-    float xv[NM], thv[NM];
 #pragma unroll
-    for (int d = 0; d < NM; ++d) {
-      const int64_t idx = (int64_t)(d < F.n ? d : F.n - 1) * Q + q;
-      xv[d] = F.x[idx];
-      thv[d] = F.theta ? F.theta[idx] : 0.f;
+      for (int d = 0; d < NM; ++d) {
+        const int64_t idx = (int64_t)(d < F.n ? d : F.n - 1) * Q + q;
+        xv[d] = F.x[idx];
+        thv[d] = F.theta ? F.theta[idx] : 0.f;
+      }
+    } else {
+      M = (double)F.part.m[q];
+      S = F.part.S[q];
+      S2 = F.part.S2[q];
     }
     const double c = (double)F.c[q];
     const double sg = (double)F.sigma;
@@ -195,13 +206,23 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
       xq[d] = 0.f;
       pg[d] = 0.f;
       if (d < F.n) {
-        double gbar = G[d] / S;
-        if (F.cv) gbar -= zsum ? Z[kZ ? d : 0] / (double)F.N : F.zbar_tab[d];
-        const double th = (double)thv[d];
+        double gbar, zs = 0.0, th;
+        if constexpr (MERGE) {
+          gbar = G[d] / S;
+          if constexpr (kZ) zs = Z[d];
+          th = (double)thv[d];
+          xq[d] = xv[d];
+        } else {
+          const int64_t idx = (int64_t)d * Q + q;
+          gbar = (double)F.part.G[idx] / S;
+          if (zsum) zs = (double)F.part.Z[idx];
+          th = F.theta ? (double)F.theta[idx] : 0.0;
+          xq[d] = F.x[idx];
+        }
+        if (F.cv) gbar -= zsum ? zs / (double)F.N : F.zbar_tab[d];
         const double gr = -(th + sg * gbar) / (c * sg * sg);
         pg[d] = (float)gr;
         F.grad[(int64_t)d * Q + q] = pg[d];
-        xq[d] = xv[d];
       }
     }
     const float vf = (float)v;
@@ -242,10 +263,10 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
   }
 }
 
-template <int NM>
+template <int NM, bool MERGE>
 __global__ __launch_bounds__(kThreads) void finalize_kernel(FinalizeArgs F) {
   if (F.done && *F.done) return;
-  finalize_block<NM>(F, blockIdx.x);
+  finalize_block<NM, MERGE>(F, blockIdx.x);
 }
 
 template <int NM>
@@ -253,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const Finali
   const int2 it = items[blockIdx.x];
   const FinalizeArgs F = args[it.x];
   if (F.done && *F.done) return;
-  finalize_block<NM>(F, it.y);
+  finalize_block<NM, true>(F, it.y);
 }
 
 // Relative L2 change over all queries from the block partials (float64, fixed order).
@@ -361,7 +382,8 @@ void finalize_launch(const FinalizeArgs& a, hipStream_t s, const ItemBatch<Final
     finalize_batched_kernel<NM><<<b->count, kThreads, 0, s>>>(b->args, b->items);
   } else {
     const dim3 grid((unsigned)((a.Q + kThreads - 1) / kThreads));
-    finalize_kernel<NM><<<grid, kThreads, 0, s>>>(a);
+    if (a.splits > 1) finalize_kernel<NM, true><<<grid, kThreads, 0, s>>>(a);
+    else finalize_kernel<NM, false><<<grid, kThreads, 0, s>>>(a);
   }
 }
 
