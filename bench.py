@@ -22,6 +22,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -226,9 +227,13 @@ def batched_study(ctx, stream, P: int = 256):
         dt_b, _ = timed(batched)
         print(f"batched study: one batched call {dt_b:.3f} s", file=sys.stderr, flush=True)
         split, _ = autotune_batched(ctx, specs, xs, N, K, t, stream=stream)
+        with tempfile.TemporaryDirectory() as tmp:
+            ctx.save_tuning(os.path.join(tmp, "tuning.txt"))
+            table = dict(line.split(" = ") for line in open(os.path.join(tmp, "tuning.txt")).read().splitlines()[1:])
+        mode = int(table.get("batch_mode", "4")) - 1
         batched()
         dt_t, out = timed(batched)
-        print(f"batched study: tuned split {split}: {dt_t:.3f} s", file=sys.stderr, flush=True)
+        print(f"batched study: tuned split {split}, launch mode {mode}: {dt_t:.3f} s", file=sys.stderr, flush=True)
     v = out.v.cpu().numpy()
     if not np.all(np.isfinite(v)):
         raise RuntimeError("non-finite values in the batched study")
@@ -240,7 +245,9 @@ def batched_study(ctx, stream, P: int = 256):
             "pairs": pairs,
             "one_call_per_problem": {"seconds": dt_one, "query_samples_per_s": pairs / dt_one},
             "batched_default_split": {"seconds": dt_b, "query_samples_per_s": pairs / dt_b},
-            "batched_autotuned": {"samples_per_split": split, "seconds": dt_t, "query_samples_per_s": pairs / dt_t},
+            "batched_autotuned": {"samples_per_split": split, "persistent": bool(mode & 1),
+                                  "concurrent_branches": bool(mode & 2), "seconds": dt_t,
+                                  "query_samples_per_s": pairs / dt_t},
             "speedup_batched_vs_one_by_one": dt_one / dt_t,
             "alu_frac_whole_call": slots / dt_t / VALU_PEAK,
             "one_call_per_problem_includes": "per-call table generation and graph recording (16-graph cache)"}

@@ -295,7 +295,11 @@ int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const float* box_lo,
  * the fastest in the context's tuning table (used by later hjg_value_grad and
  * hjg_picard_sweep calls in the same bucket); *best_blocks and *best_ms
  * receive the choice.  hjg_autotune_batched does the same for the samples per
- * split of hjg_picard_sweep_batched (2048 .. 65536), running the given batch.
+ * split of hjg_picard_sweep_batched (2048 .. 65536), running the given batch,
+ * then, at the chosen split, for its launch mode (persistent work-queue
+ * launches or one block per item; a Picard level's pair loops as parallel
+ * graph branches or one chain), kept as "batch_mode" = 1 + mode bits;
+ * *best_ms is the time of the chosen split and mode.
  * Both synchronise the stream.  hjg_tuning_save / hjg_tuning_load write and
  * read the table as text ("hjg-tuning gfx950 1", then "key = value" lines);
  * load replaces the table, and rejects files of another format.

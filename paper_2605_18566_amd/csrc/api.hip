@@ -867,13 +867,19 @@ struct SpecKey {
 
 // Samples per split in a batched launch: the batch as a whole fills the GPU,
 // so each problem is cut only into splits of about this many samples.
-// Batched sweeps run as persistent launches (resident blocks take work items
-// from a queue) unless HJG_BATCH_PERSISTENT=0 asks for one block per item.
-// The pair loops of one Picard level as parallel branches of the recorded
-// graph (default) unless HJG_BATCH_CONCURRENT=0 asks for one chain.
-bool batched_concurrent() {
-  const char* e = std::getenv("HJG_BATCH_CONCURRENT");
-  return !(e && e[0] == '0');
+// Launch mode of a batch, bit 0: persistent launches (resident blocks take
+// work items from a queue) rather than one block per item; bit 1: the pair
+// loops of one Picard level as parallel branches of the recorded graph rather
+// than one chain.  Default both; the tuning entry "batch_mode" holds the
+// autotuner's choice as mode + 1; HJG_BATCH_PERSISTENT / HJG_BATCH_CONCURRENT
+// = 0 or 1 override a bit.
+int batched_mode(const hjg_ctx* ctx) {
+  int mode = 3;
+  const auto it = ctx->tuning.find("batch_mode");
+  if (it != ctx->tuning.end() && it->second >= 1 && it->second <= 4) mode = it->second - 1;
+  if (const char* e = std::getenv("HJG_BATCH_PERSISTENT")) mode = e[0] == '0' ? (mode & ~1) : (mode | 1);
+  if (const char* e = std::getenv("HJG_BATCH_CONCURRENT")) mode = e[0] == '0' ? (mode & ~2) : (mode | 2);
+  return mode;
 }
 
 int ensure_side(hjg_ctx* ctx) {
@@ -884,11 +890,6 @@ int ensure_side(hjg_ctx* ctx) {
   }
   HJG_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
   return HJG_OK;
-}
-
-bool batched_persistent() {
-  const char* e = std::getenv("HJG_BATCH_PERSISTENT");
-  return !(e && e[0] == '0');
 }
 
 int batched_split_samples(const hjg_ctx* ctx) {
@@ -949,6 +950,8 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
   put(&grad_all, sizeof(grad_all));
   const int split_ns = batched_split_samples(ctx);
   put(&split_ns, sizeof(split_ns));
+  const int mode = batched_mode(ctx);
+  put(&mode, sizeof(mode));
 
   if (key != B.key || !B.exec) {
     drop_batch_graph(ctx);
@@ -1181,7 +1184,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
     HJG_HIP(hipMemcpy(B.items.p, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
     const int* d_items = (const int*)B.items.p;
     int* d_ctr = (int*)B.items.p + o_ctr;
-    const bool persistent = batched_persistent();
+    const bool persistent = (mode & 1) != 0;
 
     // ---- common tables (and their column means), generated once per plan
     for (int p = 0; p < P; ++p) {
@@ -1198,7 +1201,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
     HJG_HIP(hipStreamSynchronize(s));
 
     // ---- record the whole uneven multi-problem Picard loop
-    const bool concurrent = batched_concurrent();
+    const bool concurrent = (mode & 2) != 0;
     if (concurrent && (rc = ensure_side(ctx))) return rc;
     HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = persistent ? launch_fill_ints(d_ctr, n_sweeps, 0, ctx->cap) : hipSuccess;
@@ -1427,6 +1430,31 @@ extern "C" int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* 
     return rc;
   }
   ctx->tuning["batch"] = choice;
+  // then the launch mode at that split (the default mode was timed above)
+  const int mode0 = batched_mode(ctx);
+  int mode_choice = mode0;
+  for (int mode = 0; mode < 4 && rc == HJG_OK; ++mode) {
+    if (mode == mode0) continue;
+    ctx->tuning["batch_mode"] = mode + 1;
+    if (batched_mode(ctx) != mode) continue;       // an environment override pins this bit
+    rc = hjg_picard_sweep_batched(ctx, P, probs, q_off, Ns, Ks, ts, tol, x_all, v_all, grad_all, nullptr, nullptr,
+                                  hip_stream);
+    if (rc) break;
+    HJG_HIP(hipEventRecord(e0, s));
+    rc = hjg_picard_sweep_batched(ctx, P, probs, q_off, Ns, Ks, ts, tol, x_all, v_all, grad_all, nullptr, nullptr,
+                                  hip_stream);
+    if (rc) break;
+    HJG_HIP(hipEventRecord(e1, s));
+    HJG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HJG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      mode_choice = mode;
+    }
+  }
+  ctx->tuning["batch_mode"] = mode_choice + 1;
+  if (rc) return rc;
   *best_split = choice;
   *best_ms = best;
   return HJG_OK;

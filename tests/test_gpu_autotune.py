@@ -53,9 +53,10 @@ def test_autotune_sweep_keeps_parity(ctx, tmp_path):
     other.close()
 
 
-def test_autotune_batched_choice_is_the_plan_it_runs(ctx, monkeypatch):
+def test_autotune_batched_choice_is_the_plan_it_runs(ctx, monkeypatch, tmp_path):
     # after tuning, the default batched call must be bit-identical to one that
-    # forces the chosen samples-per-split
+    # forces the chosen samples-per-split, and to one in the other launch mode
+    # (one block per item, one chain); the chosen mode is in the saved table
     from paper_2605_18566_amd import autotune_batched, picard_sweep_batched
     batch = workloads.c3_batch(P=10, scale=0.03, trial=4)
     xs = [to_dev(np.ascontiguousarray(workloads.queries(bp.w, trial=11 + i).T)) for i, bp in enumerate(batch)]
@@ -69,3 +70,11 @@ def test_autotune_batched_choice_is_the_plan_it_runs(ctx, monkeypatch):
     monkeypatch.setenv("HJG_BATCH_SPLIT", str(split))
     b = picard_sweep_batched(ctx, specs, xs, *args)
     assert torch.equal(va, b.v)
+    path = str(tmp_path / "tuning.txt")
+    ctx.save_tuning(path)
+    entries = dict(line.split(" = ") for line in open(path).read().splitlines()[1:])
+    assert int(entries["batch"]) == split and 1 <= int(entries["batch_mode"]) <= 4
+    monkeypatch.setenv("HJG_BATCH_PERSISTENT", "0")
+    monkeypatch.setenv("HJG_BATCH_CONCURRENT", "0")
+    c = picard_sweep_batched(ctx, specs, xs, *args)
+    assert torch.equal(va, c.v)
