@@ -150,6 +150,29 @@ def test_grad_optional_nan_kept_and_empty(ctx):
         avoid_project(bad, xd, va)
 
 
+@pytest.mark.parametrize("Q", [1, 2, 63, 65])
+def test_one_dimension_and_tiny_batches(ctx, Q):
+    """n = 1 (an interval as the avoid set) at batch sizes below and around one
+    wave: values, flags and gradients equal the oracle's."""
+    from paper_2605_18566_amd import avoid_project
+    rng = np.random.default_rng(300 + Q)
+    fields = dict(n=1, ham="quadratic", datum="ball", datum_p=(1, 0.5), nu=0.05)
+    x = rng.uniform(-1.0, 1.0, (Q, 1)).astype(np.float32).astype(np.float64)
+    v = rng.uniform(-1.0, 1.0, Q).astype(np.float32)
+    g = rng.normal(size=(Q, 1)).astype(np.float32)
+    vd, gd = to_dev(v), to_dev(soa(g))
+    act = avoid_project(gpu_problem(fields), to_dev(soa(x)), vd, gd, want_active=True)
+    torch.cuda.synchronize()
+    rv, rg, ra = avoid.project(oracle_problem(fields), x, v.astype(np.float64), g.astype(np.float64))
+    lv, _ = avoid.obstacle_level(oracle_problem(fields), x)
+    tol = 2e-6 * (1.0 + np.abs(lv))
+    clear = np.abs(-lv - v) > tol
+    assert np.all(np.abs(vd.cpu().numpy() - rv) <= tol)
+    a = act.cpu().numpy().astype(bool)
+    assert np.array_equal(a[clear], ra[clear])
+    np.testing.assert_allclose(gd.cpu().numpy().T[clear], rg[clear], rtol=0, atol=1e-6)
+
+
 def test_reach_avoid_step_matches_oracle(ctx):
     """One reach-avoid time step on the relative Dubins tube (horizon 0.1,
     K = 3, tilt, common draws): Algorithm 1 then the projection onto a union
