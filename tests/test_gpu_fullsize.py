@@ -102,3 +102,41 @@ def test_c5_full_size_single_sweep_gradient(ctx):
     gt = grad_tol(ref.grad, c[sel], sigma, w.N)
     print(f"[C5 one sweep gradient] max |dgrad| {dg.max():.3e}, worst |dgrad|/tol {np.max(dg / gt):.3f}", flush=True)
     assert np.all(dg <= gt)
+
+
+def test_c3_full_batch_sampled_states(ctx):
+    """The 256-problem uneven batch at full size in the benchmark's launch
+    configuration (one recorded graph, persistent launches, parallel branches,
+    the default split) against the oracle on sampled states of seven problems
+    (the widest and narrowest among them), each recomputed one by one over the
+    problem's full K; no tolerance stops the loop, so states do not interact."""
+    from paper_2605_18566_amd import picard_sweep_batched
+    batch = workloads.c3_batch(P=256)
+    xs = [np.ascontiguousarray(workloads.queries(bp.w, trial=1 + i).T) for i, bp in enumerate(batch)]
+    specs = [gpu_problem(workloads.c3_fields(bp), problem_id=bp.problem_id) for bp in batch]
+    print("[C3 full batch] 256 problems", flush=True)
+    out = picard_sweep_batched(ctx, specs, [to_dev(x) for x in xs], [bp.w.N for bp in batch],
+                               [bp.w.K for bp in batch], [bp.w.t for bp in batch])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2605)
+    cost = np.array([bp.w.N * bp.w.n * bp.w.K for bp in batch])
+    ns = np.array([bp.w.n for bp in batch])
+    cheap = np.flatnonzero(cost <= 2e7)
+    chosen = {int(np.argmax(np.where(cost <= 1.2e8, ns, -1))), int(cheap[np.argmin(ns[cheap])])}
+    chosen |= {int(p) for p in rng.choice(cheap, 5, replace=False)}
+    bad = total = 0
+    for p in sorted(chosen):
+        bp = batch[p]
+        v = out.v[int(out.q_off[p]):int(out.q_off[p + 1])].cpu().numpy()
+        sel = rng.choice(bp.w.Q, 3, replace=False)
+        pb = oracle_problem(workloads.c3_fields(bp))
+        pb.problem_id = bp.problem_id
+        ref = estimator.picard(pb, xs[p].T[sel].astype(np.float64), bp.w.t, bp.w.N, bp.w.K)
+        sigma = np.sqrt(pb.delta * bp.w.t)
+        vt = value_tol(ref.v, ref.c, ref.theta, sigma, ref.lmax)
+        ratio = _report(f"C3 problem {p}: n={bp.w.n} Q={bp.w.Q} N={bp.w.N} K={bp.w.K}", v[sel] - ref.v, vt)
+        bad += int(np.sum(ratio > 10.0))
+        total += len(sel)
+    # as for the single-problem full sweep: 10x the one-sweep tolerance (float32
+    # differences of an iterate feed the next coefficient) on all but one state
+    assert total >= 21 and bad <= 1
