@@ -15,7 +15,8 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    available here)
   estimator.value_grad           : closed forms (quadratic H with quadratic and
                                    linear data), 1D folded-normal closed form,
-                                   2D disk quadrature, c -> 0 limit, tilt
+                                   2D disk quadrature, finite-difference grid
+                                   solves of the PDE in 1D and 2D, c -> 0 limit, tilt
                                    invariance, Stein vs finite differences,
                                    N^-1/2 rate
   estimator.picard               : quadratic-H fixed point in one step,
