@@ -157,20 +157,28 @@ def surrogate_study(ctx, stream):
     rms = lambda v: float(torch.sqrt(torch.mean((v - vj) ** 2)))
     sv, _ = sur.predict(x, w.t)
     plain, surr = [], []
-    for N in (1 << 12, 1 << 14, 1 << 16):
+    for N in (1 << 12, 1 << 14, 1 << 16, 1 << 18):
         o, sec = timed(lambda: picard_sweep(ctx, spec, x, w.t, N, w.K, stream=stream))
         plain.append({"N": N, "K": w.K, "rms_v": rms(o.v), "ms": sec * 1e3})
     for tol in (1e-3, 1e-2):
-        for N in (1 << 12, 1 << 14, 1 << 16):
+        for N in (1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16):
             (v, g, fb, nfb), sec = timed(lambda: surrogate_sweep(ctx, sur, spec, x, w.t, N, 2, w.N, w.K, tol,
                                                                  stream=stream))
             surr.append({"N_s": N, "K_s": 2, "tol": tol, "rms_v": rms(v), "ms": sec * 1e3,
                          "fallback": nfb / w.Q})
-    target = plain[-1]["rms_v"]
-    speedup = {}
+    # equal RMS: the plain sweep at the workload's N = 65,536 sets the target;
+    # the same comparison against the plain sweep at 4x the samples (a
+    # tighter target; the judge's own error, ~1/4 of the N = 65,536 one, is
+    # part of every RMS)
+    ref = next(r for r in plain if r["N"] == w.N)
+    target = ref["rms_v"]
+    speedup, speedup_4n = {}, {}
+    big = plain[-1]
     for tol in (1e-3, 1e-2):
         ok = [r["ms"] for r in surr if r["tol"] == tol and r["rms_v"] <= target]
-        speedup[f"tol={tol:g}"] = (plain[-1]["ms"] / min(ok)) if ok else None
+        speedup[f"tol={tol:g}"] = (ref["ms"] / min(ok)) if ok else None
+        ok = [r["ms"] for r in surr if r["tol"] == tol and r["rms_v"] <= big["rms_v"]]
+        speedup_4n[f"tol={tol:g}"] = (big["ms"] / min(ok)) if ok else None
     sur.close()
     return {"workload": f"{w.name}: n=45, H=|p|^2/2, 15-disc union, nu={w.nu}, t={w.t}, bf16 draws, Q={w.Q}",
             "network": "46 -> 4 x 256 SiLU -> 46, bf16 MFMA forward/backward, fp32 master, AdamW",
@@ -181,7 +189,9 @@ def surrogate_study(ctx, stream):
             "surrogate_alone_rms_v": rms(sv),
             "plain": plain, "surrogate": surr,
             "target_rms_v": target,
-            "speedup_at_equal_rms": speedup}
+            "speedup_at_equal_rms": speedup,
+            "target_rms_v_plain_4N": big["rms_v"],
+            "speedup_at_equal_rms_vs_plain_4N": speedup_4n}
 
 
 def batched_study(ctx, stream, P: int = 256):
