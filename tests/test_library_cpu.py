@@ -93,6 +93,19 @@ def test_version_and_error_paths_without_device(lib):
     assert lib.hjg_surrogate_save(None, b"/nonexistent/x") == _lib.HJG_EINVAL
     assert lib.hjg_tuning_save(None, b"/nonexistent/x") == _lib.HJG_EINVAL
     assert lib.hjg_tuning_load(None, b"/nonexistent/x") == _lib.HJG_EINVAL
+    # obstacle projection: every check runs before any device work
+    assert lib.hjg_avoid_project(None, 4, None, None, None, None, None) == _lib.HJG_EINVAL
+    ob = _lib.Problem()
+    ob.n, ob.nu, ob.c_min, ob.c_max = 2, 0.05, 0.01, 1e4
+    ob.datum = _lib.DATUMS["ball"]
+    ob.datum_p[0], ob.datum_p[1] = 2.0, 0.5
+    assert lib.hjg_avoid_project(C.byref(ob), -1, None, None, None, None, None) == _lib.HJG_EINVAL
+    assert lib.hjg_avoid_project(C.byref(ob), 0, None, None, None, None, None) == _lib.HJG_OK
+    assert lib.hjg_avoid_project(C.byref(ob), 4, None, None, None, None, None) == _lib.HJG_EINVAL
+    assert b"required" in lib.hjg_last_error()
+    ob.datum = _lib.DATUMS["disc_union"]                 # needs its centres
+    ob.datum_p[0], ob.datum_p[1] = 0.5, 2.0
+    assert lib.hjg_avoid_project(C.byref(ob), 0, None, None, None, None, None) == _lib.HJG_EINVAL
     lib.hjg_ctx_destroy(None)
 
 
