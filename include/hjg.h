@@ -441,9 +441,9 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
  * labels.
  * ------------------------------------------------------------------------
  */
-/* Obstacle projection in place.  obstacle: a problem record that passes the
- * usual checks, of which only n and the datum fields (datum, datum_p,
- * datum_aux) are used: l_A is that datum (same kinks and tie rules as the
+/* Obstacle projection in place.  obstacle: a problem record of which only n
+ * and the datum fields (datum, datum_p, datum_aux) are read and checked (the
+ * other fields are ignored): l_A is that datum (same kinks and tie rules as the
  * sweep's; knn_balls aux is indexed by the state index q < Q).  x device
  * [n][Q] (dimension-major, float32); v device [Q] in/out; grad device [n][Q]
  * in/out or NULL (then only v changes); active device uint8 [Q] out or NULL:

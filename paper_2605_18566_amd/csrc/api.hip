@@ -133,6 +133,8 @@ int ensure(hjg_ctx* ctx, DevBuf& b, size_t bytes) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
+int check_datum(const hjg_problem* p);
+
 int check_problem(const hjg_problem* p) {
   if (!p) return fail(HJG_EINVAL, "problem is NULL");
   if (p->n < 1 || p->n > kMaxN) return fail(HJG_EINVAL, "n must be in [1, 48]");
@@ -178,6 +180,13 @@ int check_problem(const hjg_problem* p) {
     default:
       return fail(HJG_EINVAL, "unknown Hamiltonian");
   }
+  return check_datum(p);
+}
+
+// The state dimension and the datum fields (kind, parameters, auxiliary data).
+int check_datum(const hjg_problem* p) {
+  if (!p) return fail(HJG_EINVAL, "problem is NULL");
+  if (p->n < 1 || p->n > kMaxN) return fail(HJG_EINVAL, "n must be in [1, 48]");
   switch (p->datum) {
     case HJG_L_HALF_SQNORM:
       break;
@@ -400,6 +409,7 @@ int check_common(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, double t, int32_
 namespace hjg {
 namespace detail {
 int check_problem(const hjg_problem* p) { return ::check_problem(p); }
+int check_datum(const hjg_problem* p) { return ::check_datum(p); }
 DatumP datum_params(const hjg_problem* p) { return ::datum_params(p); }
 HamP ham_params(const hjg_problem* p) { return ::ham_params(p); }
 uint32_t make_tag(uint32_t pid, uint32_t step, uint32_t iter) { return ::make_tag(pid, step, iter); }

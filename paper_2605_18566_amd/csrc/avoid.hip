@@ -49,7 +49,7 @@ int hjg_avoid_project(const hjg_problem* obstacle, int64_t Q, const float* x, fl
                       uint8_t* active, void* hip_stream) {
   const hjg::detail::TraceRange trace_("hjg_avoid_project");
   int rc;
-  if ((rc = hjg::detail::check_problem(obstacle))) return rc;
+  if ((rc = hjg::detail::check_datum(obstacle))) return rc;
   if (Q < 0 || Q > ((int64_t)1 << 40)) return fail(HJG_EINVAL, "Q must be in [0, 2^40]");
   if (Q == 0) return HJG_OK;
   if (!x || !v) return fail(HJG_EINVAL, "x and v are required");

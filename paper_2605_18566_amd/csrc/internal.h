@@ -18,6 +18,9 @@ namespace detail {
 
 // Argument checks of a problem record (the same as every sweep entry point).
 HJG_HIDDEN int check_problem(const hjg_problem* p);
+// Only the state dimension and the datum fields (for records that describe a
+// level function, such as an avoid set).
+HJG_HIDDEN int check_datum(const hjg_problem* p);
 HJG_HIDDEN DatumP datum_params(const hjg_problem* p);
 HJG_HIDDEN HamP ham_params(const hjg_problem* p);
 // Philox counter tag of (problem, time step, iteration).

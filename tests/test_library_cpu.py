@@ -106,6 +106,13 @@ def test_version_and_error_paths_without_device(lib):
     ob.datum = _lib.DATUMS["disc_union"]                 # needs its centres
     ob.datum_p[0], ob.datum_p[1] = 0.5, 2.0
     assert lib.hjg_avoid_project(C.byref(ob), 0, None, None, None, None, None) == _lib.HJG_EINVAL
+    # only n and the datum fields are checked: a 48-dimensional capture set with
+    # fields a sweep would reject (fresh draws at n = 48, nu = NaN) is accepted
+    ob.n, ob.datum, ob.sample_mode, ob.nu = 48, _lib.DATUMS["capture"], 0, float("nan")
+    ob.datum_p[0] = 0.4
+    assert lib.hjg_avoid_project(C.byref(ob), 0, None, None, None, None, None) == _lib.HJG_OK
+    assert lib.hjg_value_grad(None, C.byref(ob), 0, None, 0.5, 16, 0, 0, None, None, None, None, None, 0,
+                              None) == _lib.HJG_EINVAL
     lib.hjg_ctx_destroy(None)
 
 
