@@ -878,9 +878,9 @@ struct SpecKey {
 // Samples per split in a batched launch: the batch as a whole fills the GPU,
 // so each problem is cut only into splits of about this many samples.
 // Launch mode of a batch, bit 0: persistent launches (resident blocks take
-// work items from a queue) rather than one block per item; bit 1: the pair
-// loops of one Picard level as parallel branches of the recorded graph rather
-// than one chain.  Default both; the tuning entry "batch_mode" holds the
+// work items from a queue) rather than one block per item; bit 1: the chains
+// of the kernel specialisations (each its problems' levels in order) as
+// parallel branches of the recorded graph rather than one after another.  Default both; the tuning entry "batch_mode" holds the
 // autotuner's choice as mode + 1; HJG_BATCH_PERSISTENT / HJG_BATCH_CONCURRENT
 // = 0 or 1 override a bit.
 int batched_mode(const hjg_ctx* ctx) {
@@ -1145,44 +1145,67 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       }
     };
     add_q_items(0, 0);
-    for (int k = 0; k < Kmax; ++k) {
-      std::map<SpecKey, std::vector<int>> groups;
-      for (int p = 0; p < P; ++p) {
-        if (Ks[p] <= k) continue;
-        const hjg_problem& pr = probs[p];
-        const SpecKey sk{pr.datum, n_bucket(pr.n), (pr.datum == HJG_L_MIN_PAIR_DISKS || pr.datum == HJG_L_CAPTURE) ? pr.n / 3 : 0, pl[p].mfma,
-                         pl[p].bf16};
-        groups[sk].push_back(p);
-      }
-      for (auto& kv : groups) {
+    // One chain per kernel specialisation: its problems' levels in order
+    // (sweep, finalize, reduce), independent of the other chains, so the
+    // chains run as parallel graph branches without a barrier per level.
+    std::map<SpecKey, std::vector<int>> groups;
+    for (int p = 0; p < P; ++p) {
+      const hjg_problem& pr = probs[p];
+      const SpecKey sk{pr.datum, n_bucket(pr.n),
+                       (pr.datum == HJG_L_MIN_PAIR_DISKS || pr.datum == HJG_L_CAPTURE) ? pr.n / 3 : 0, pl[p].mfma,
+                       pl[p].bf16};
+      groups[sk].push_back(p);
+    }
+    struct Chain {
+      size_t first, last;   // launches [first, last)
+      double cost;
+    };
+    std::vector<Chain> chains;
+    for (auto& kv : groups) {
+      const std::vector<int>& G = kv.second;
+      Chain ch{launches.size(), 0, 0.0};
+      int Kg = 0;
+      for (int p : G) Kg = std::max(Kg, (int)Ks[p]);
+      for (int k = 0; k < Kg; ++k) {
         struct It { int p, qb, sp; double cost; };
         std::vector<It> its;
-        for (int p : kv.second)
+        std::vector<int> live;
+        for (int p : G) {
+          if (Ks[p] <= k) continue;
+          live.push_back(p);
           for (int64_t qb = 0; qb < pl[p].qb_sweep; ++qb)
             for (int sp = 0; sp < pl[p].splits; ++sp) {
               const int samples = std::min<int64_t>(pl[p].ns, (int64_t)Ns[p] - (int64_t)sp * pl[p].ns);
               its.push_back(It{p, (int)qb, sp, (double)samples * (probs[p].n + 10)});
             }
+        }
         std::stable_sort(its.begin(), its.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
         while (items.size() % 4) items.push_back(0);     // int4 records: 16-byte aligned
-        const int64_t o = (int64_t)items.size();
+        int64_t o = (int64_t)items.size();
         for (const It& it : its) {
           items.push_back(it.p);
           items.push_back(it.qb);
           items.push_back(it.sp);
           items.push_back(0);
+          ch.cost += it.cost;
         }
-        launches.push_back(Launch{1, kv.second[0], o, (int)its.size(), k});
+        launches.push_back(Launch{1, live[0], o, (int)its.size(), k});
+        // finalize: (problem, 256-state block) records; one register bucket per chain
+        while (items.size() % 2) items.push_back(0);     // int2 records: 8-byte aligned
+        o = (int64_t)items.size();
+        int cnt = 0;
+        for (int p : live)
+          for (int64_t b = 0; b < pl[p].qb256; ++b, ++cnt) {
+            items.push_back(p);
+            items.push_back((int)b);
+          }
+        launches.push_back(Launch{2, live[0], o, cnt, k});
+        o = (int64_t)items.size();
+        for (int p : live) items.push_back(p);
+        launches.push_back(Launch{3, 0, o, (int)live.size(), k});
       }
-      add_q_items(2, k);
-      const int64_t o = (int64_t)items.size();
-      int cnt = 0;
-      for (int p = 0; p < P; ++p)
-        if (Ks[p] > k) {
-          items.push_back(p);
-          ++cnt;
-        }
-      launches.push_back(Launch{3, 0, o, cnt, k});
+      ch.last = launches.size();
+      chains.push_back(ch);
     }
     // one work-queue head per sweep launch, after the item records
     int n_sweeps = 0;
@@ -1215,44 +1238,54 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
     if (concurrent && (rc = ensure_side(ctx))) return rc;
     HJG_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = persistent ? launch_fill_ints(d_ctr, n_sweeps, 0, ctx->cap) : hipSuccess;
-    int sweep_i = 0;
-    for (size_t li = 0; li < launches.size(); ++li) {
-      if (e != hipSuccess) break;
+    // sweep launch i uses work-queue head d_ctr[i], in launch-list order
+    std::vector<int> qhead(launches.size(), 0);
+    for (size_t li = 0, i = 0; li < launches.size(); ++li)
+      if (launches[li].kind == 1) qhead[li] = (int)i++;
+    auto record = [&](size_t li, hipStream_t st) -> hipError_t {
       const Launch& L = launches[li];
-      size_t lj = li;
-      while (lj < launches.size() && launches[lj].kind == 1) ++lj;
-      if (concurrent && L.kind == 1 && lj - li > 1) {
-        // the level's pair loops: fork from the recording stream onto the side
-        // streams (round robin), join back before the level's finalize
-        const int ns = (int)std::min<size_t>(lj - li, hjg_ctx::kSide);
-        e = hipEventRecord(ctx->fork_ev, ctx->cap);
-        for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->side[j], ctx->fork_ev, 0);
-        for (size_t m = li; m < lj && e == hipSuccess; ++m) {
-          const Launch& M = launches[m];
-          SweepBatch b{d_sa, (const int4*)(d_items + M.off), M.count, persistent ? d_ctr + sweep_i : nullptr};
-          ++sweep_i;
-          e = launch_sweep(sa[M.rep], 0, pl[M.rep].bf16, ctx->side[(m - li) % ns], &b);
-        }
-        for (int j = 0; j < ns && e == hipSuccess; ++j) {
-          e = hipEventRecord(ctx->join_ev[j], ctx->side[j]);
-          if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cap, ctx->join_ev[j], 0);
-        }
-        li = lj - 1;
-        continue;
-      }
       if (L.kind == 0) {
         ItemBatch<InitArgs> b{d_ia, (const int2*)(d_items + L.off), L.count};
-        e = launch_init(ia[L.rep], ctx->cap, &b);
-      } else if (L.kind == 1) {
-        SweepBatch b{d_sa, (const int4*)(d_items + L.off), L.count, persistent ? d_ctr + sweep_i : nullptr};
-        ++sweep_i;
-        e = launch_sweep(sa[L.rep], 0, pl[L.rep].bf16, ctx->cap, &b);
-      } else if (L.kind == 2) {
-        ItemBatch<FinalizeArgs> b{d_fa, (const int2*)(d_items + L.off), L.count};
-        e = launch_finalize(fa[L.rep], ctx->cap, &b);
-      } else {
-        e = launch_reduce_batched(d_ra, d_items + L.off, L.count, L.level, ctx->cap);
+        return launch_init(ia[L.rep], st, &b);
       }
+      if (L.kind == 1) {
+        SweepBatch b{d_sa, (const int4*)(d_items + L.off), L.count, persistent ? d_ctr + qhead[li] : nullptr};
+        return launch_sweep(sa[L.rep], 0, pl[L.rep].bf16, st, &b);
+      }
+      if (L.kind == 2) {
+        ItemBatch<FinalizeArgs> b{d_fa, (const int2*)(d_items + L.off), L.count};
+        return launch_finalize(fa[L.rep], st, &b);
+      }
+      return launch_reduce_batched(d_ra, d_items + L.off, L.count, L.level, st);
+    };
+    const size_t n_init = chains.empty() ? launches.size() : chains[0].first;
+    for (size_t li = 0; li < n_init && e == hipSuccess; ++li) e = record(li, ctx->cap);
+    if (concurrent && chains.size() > 1) {
+      // chains onto the side streams, heaviest first to the least loaded
+      // stream; join back at the end
+      const int ns = (int)std::min<size_t>(chains.size(), hjg_ctx::kSide);
+      std::vector<size_t> order(chains.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](size_t a, size_t b) { return chains[a].cost > chains[b].cost; });
+      std::vector<double> load(ns, 0.0);
+      std::vector<std::vector<size_t>> lane(ns);
+      for (size_t c : order) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[j] += chains[c].cost;
+        lane[j].push_back(c);
+      }
+      if (e == hipSuccess) e = hipEventRecord(ctx->fork_ev, ctx->cap);
+      for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->side[j], ctx->fork_ev, 0);
+      for (int j = 0; j < ns && e == hipSuccess; ++j)
+        for (size_t c : lane[j])
+          for (size_t li = chains[c].first; li < chains[c].last && e == hipSuccess; ++li) e = record(li, ctx->side[j]);
+      for (int j = 0; j < ns && e == hipSuccess; ++j) {
+        e = hipEventRecord(ctx->join_ev[j], ctx->side[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cap, ctx->join_ev[j], 0);
+      }
+    } else {
+      for (size_t li = n_init; li < launches.size() && e == hipSuccess; ++li) e = record(li, ctx->cap);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(ctx->cap, &graph);
