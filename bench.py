@@ -153,19 +153,21 @@ def surrogate_study(ctx, stream):
     spec = ProblemSpec(**f)
     judge = picard_sweep(ctx, ProblemSpec(**dict(f, seed=f["seed"] + 777)), x, w.t, 1 << 20, w.K, time_step=3,
                          stream=stream)
-    vj = judge.v.clone()
+    vj, gj = judge.v.clone(), judge.grad.clone()
     rms = lambda v: float(torch.sqrt(torch.mean((v - vj) ** 2)))
+    rms_g = lambda g: float(torch.sqrt(torch.mean(torch.sum((g - gj) ** 2, 0))))
     sv, _ = sur.predict(x, w.t)
     plain, surr = [], []
     for N in (1 << 12, 1 << 14, 1 << 16, 1 << 18):
         o, sec = timed(lambda: picard_sweep(ctx, spec, x, w.t, N, w.K, stream=stream))
-        plain.append({"N": N, "K": w.K, "rms_v": rms(o.v), "ms": sec * 1e3})
+        plain.append({"N": N, "K": w.K, "rms_v": rms(o.v), "rms_grad": rms_g(o.grad), "ms": sec * 1e3})
     for tol in (1e-3, 1e-2):
-        for N in (1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16):
-            (v, g, fb, nfb), sec = timed(lambda: surrogate_sweep(ctx, sur, spec, x, w.t, N, 2, w.N, w.K, tol,
-                                                                 stream=stream))
-            surr.append({"N_s": N, "K_s": 2, "tol": tol, "rms_v": rms(v), "ms": sec * 1e3,
-                         "fallback": nfb / w.Q})
+        for K_s in (1, 2):
+            for N in (1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16):
+                (v, g, fb, nfb), sec = timed(lambda: surrogate_sweep(ctx, sur, spec, x, w.t, N, K_s, w.N, w.K, tol,
+                                                                     stream=stream))
+                surr.append({"N_s": N, "K_s": K_s, "tol": tol, "rms_v": rms(v), "rms_grad": rms_g(g),
+                             "ms": sec * 1e3, "fallback": nfb / w.Q})
     # equal RMS: the plain sweep at the workload's N = 65,536 sets the target;
     # the same comparison against the plain sweep at 4x the samples (a
     # tighter target; the judge's own error, ~1/4 of the N = 65,536 one, is
