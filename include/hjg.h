@@ -41,6 +41,12 @@
  *    query).
  *  - Not thread-safe per context: calls that share an hjg_ctx must be
  *    serialised by the caller.
+ *  - Environment switches, read per call, select alternative paths for
+ *    comparison (the defaults are the tuned ones): HJG_NO_MFMA=1,
+ *    HJG_TARGET_BLOCKS=n, HJG_NO_GRAPH=1, HJG_BATCH_SPLIT=n,
+ *    HJG_BATCH_PERSISTENT=0|1, HJG_BATCH_CONCURRENT=0|1, HJG_TUBE_FUSED=0,
+ *    HJG_TUBE_ROWS=n.  Results do not depend on them except through the
+ *    vector-ALU / matrix-core choice (float32 rounding order).
  */
 #ifndef HJG_H
 #define HJG_H
