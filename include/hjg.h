@@ -45,8 +45,10 @@
  *    comparison (the defaults are the tuned ones): HJG_NO_MFMA=1,
  *    HJG_TARGET_BLOCKS=n, HJG_NO_GRAPH=1, HJG_BATCH_SPLIT=n,
  *    HJG_BATCH_PERSISTENT=0|1, HJG_BATCH_CONCURRENT=0|1, HJG_TUBE_FUSED=0,
- *    HJG_TUBE_ROWS=n.  Results do not depend on them except through the
- *    vector-ALU / matrix-core choice (float32 rounding order).
+ *    HJG_TUBE_ROWS=n.  The graph, launch-mode and row-chunk switches give
+ *    the same bits; the path and split switches (HJG_NO_MFMA,
+ *    HJG_TARGET_BLOCKS, HJG_BATCH_SPLIT, HJG_TUBE_FUSED) change the float32
+ *    summation order, so results move at rounding level.
  */
 #ifndef HJG_H
 #define HJG_H
