@@ -147,3 +147,21 @@ def test_persistent_launch_matches_one_block_per_item(monkeypatch):
         c.close()
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
+def test_parallel_chains_match_one_chain(monkeypatch):
+    # the specialisation chains as parallel graph branches or recorded one
+    # after another: the same launches in another order, so the same bits
+    from paper_2605_18566_amd import Context
+    batch, xs = small_batch(P=12, trial=6)
+    assert len({(bp.w.n, bp.w.n >= 16) for bp in batch}) > 2
+    outs = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HJG_BATCH_CONCURRENT", mode)
+        c = Context(0)
+        o = run_batched(c, batch, xs)
+        outs.append((o.v.clone(), o.grad.clone(), o.resid_hist.copy(), o.iters.copy()))
+        c.close()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+    np.testing.assert_array_equal(outs[0][3], outs[1][3])
