@@ -9,10 +9,11 @@ device path; the Gaussian draws come from its own Philox4x32-10
 implementation (``oracle.philox``).
 
 Parity status per function (what pins it, see tests/test_oracle_*.py):
-  philox.philox4x32_10 / normals : statistical tests only, plus bit agreement
-                                   with the independent device implementation
-                                   (no published known-answer vectors are
-                                   available here)
+  philox.philox4x32_10 / normals : word for word against an independent
+                                   implementation (Triton's philox, run by its
+                                   CPU interpreter) over several keys and all
+                                   four counter words; structural and
+                                   statistical tests
   estimator.value_grad           : closed forms (quadratic H with quadratic and
                                    linear data), 1D folded-normal closed form,
                                    2D disk quadrature, finite-difference grid
@@ -21,7 +22,9 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    N^-1/2 rate
   estimator.picard               : quadratic-H fixed point in one step,
                                    deterministic contraction under common
-                                   random numbers; for non-quadratic H the
+                                   random numbers; the warm start v0 (zero
+                                   first residual at a p-independent fixed
+                                   point, NaN starts flagged); for non-quadratic H the
                                    Picard fixed point is "parity unpinned"
                                    against the viscous solution (the paper's
                                    quasi-linearisation defect is not computable)
@@ -47,9 +50,15 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                                    radius, the two saddle cells by hand
   model.hamiltonian (Dubins,     : brute-force max-min over control grids
     multi-pursuer game)
-  model.coefficient              : direct evaluation checks (sign, clip, eta)
+  model.coefficient /            : the general branch gives exactly 1/delta for
+    frozen_coefficient             H = |p|^2/2 with eta = 0; hand-worked Dubins
+                                   values (both signs of the p2 term, tube
+                                   form); sign-keeping clip
   model.datum (capture)          : a hand-built configuration; its gradient
                                    against central differences
+  model.datum / datum_grad       : a brute-force loop over pairs (m = 1..15,
+    (min_pair_disks)               r = 0), central differences, ties to the
+                                   lowest pair and the centre kink by hand
   knn.knn                        : a k-d tree (scipy) on random points, the
                                    unit-lattice closed form, duplicate points
                                    and float32 near-ties

@@ -122,7 +122,8 @@ class PicardResult:
     grad: np.ndarray
     c: np.ndarray            # coefficient frozen in the last executed iteration
     ess: np.ndarray
-    flags: np.ndarray        # per-query relative change > tol at the last iteration
+    flags: np.ndarray        # per-query relative change not <= tol at the last iteration
+                             # (a NaN change is flagged)
     resid_hist: np.ndarray   # global relative L2 change per executed iteration
     iters_done: int
     lmax: np.ndarray
@@ -135,12 +136,17 @@ def v_floor(pb: model.Problem, t: float) -> float:
 
 
 def picard(pb: model.Problem, x: np.ndarray, t: float, N: int, K: int, tol: float = 0.0,
-           time_step: int = 0, p0: Optional[np.ndarray] = None) -> PicardResult:
-    """Algorithm 1 at the evaluation states x[Q, n] and horizon t."""
+           time_step: int = 0, p0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None) -> PicardResult:
+    """Algorithm 1 at the evaluation states x[Q, n] and horizon t.
+
+    The "Fix" step starts the loop from v^(0) = l(x) and p^(0) = D l(x); a warm
+    start replaces either by the given v0[Q] or p0[Q, n] (the first relative
+    change, and so the first residual and flags, is measured from v0).
+    """
     x = np.asarray(x, dtype=np.float64)
     Q, n = x.shape
     sigma = np.sqrt(pb.delta * t)
-    v_prev = datum_at(pb, x)
+    v_prev = datum_at(pb, x) if v0 is None else np.asarray(v0, dtype=np.float64).copy()
     p = model.datum_grad(pb, x, pb.datum_aux) if p0 is None else np.asarray(p0, dtype=np.float64)
     hist = []
     est = None
@@ -159,7 +165,7 @@ def picard(pb: model.Problem, x: np.ndarray, t: float, N: int, K: int, tol: floa
         p = est.grad
         if r < tol:
             break
-    return PicardResult(est.v, est.grad, c, est.ess, rq > tol, np.array(hist), len(hist), est.lmax, theta)
+    return PicardResult(est.v, est.grad, c, est.ess, ~(rq <= tol), np.array(hist), len(hist), est.lmax, theta)
 
 
 def datum_at(pb: model.Problem, x: np.ndarray) -> np.ndarray:
@@ -206,4 +212,4 @@ def tube_step(pb: model.Problem, x: np.ndarray, t_prev: float, dt: float, N: int
         p = est.grad
         if r < tol:
             break
-    return PicardResult(est.v, est.grad, c, est.ess, rq > tol, np.array(hist), len(hist), est.lmax, theta)
+    return PicardResult(est.v, est.grad, c, est.ess, ~(rq <= tol), np.array(hist), len(hist), est.lmax, theta)

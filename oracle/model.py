@@ -252,9 +252,20 @@ def coefficient(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
     H = hamiltonian(pb, x, p)
     if pb.tube:
         H = np.minimum(H, 0.0)
-    c_raw = (2.0 / pb.delta) * H / (np.sum(p * p, axis=1) + pb.eta)
+    return frozen_coefficient(H, p, pb.delta, pb.eta, pb.c_min, pb.c_max)
+
+
+def frozen_coefficient(H: np.ndarray, p: np.ndarray, delta: float, eta: float, c_min: float,
+                       c_max: float) -> np.ndarray:
+    """The general branch of the coefficient from Hamiltonian values H[Q] and p[Q, n].
+
+    c_raw = (2/delta) H / (|p|^2 + eta) (the coefficient definition with the
+    regularised denominator), then |c| clipped to [c_min, c_max] with the sign
+    of c_raw kept and sign(0) = +1 (remark on the sign of the coefficient).
+    """
+    c_raw = (2.0 / delta) * np.asarray(H, dtype=np.float64) / (np.sum(p * p, axis=1) + eta)
     sgn = np.where(c_raw < 0, -1.0, 1.0)
-    return sgn * np.clip(np.abs(c_raw), pb.c_min, pb.c_max)
+    return sgn * np.clip(np.abs(c_raw), c_min, c_max)
 
 
 def tilt(pb: Problem, sigma: float, c: np.ndarray, p: np.ndarray) -> np.ndarray:

@@ -462,3 +462,146 @@ def test_picard_early_exit_and_flags():
     res = estimator.picard(pb, x, 0.5, 2048, K=5, tol=1e-6)
     assert res.iters_done == 2 and res.resid_hist[-1] == 0.0
     assert not res.flags.any()
+
+
+# ------------------------------------------- stacked disc pairs: the datum of the Dubins workloads
+def _min_pair_disks_brute(y, r):
+    """min over pairs j of the planar distance |(y[3j], y[3j+1])| minus r, one state at a time."""
+    out = np.empty(len(y))
+    for q, yq in enumerate(y):
+        best = np.inf
+        for j in range(len(yq) // 3):
+            d = np.sqrt(yq[3 * j] ** 2 + yq[3 * j + 1] ** 2)
+            if d < best:
+                best = d
+        out[q] = best - r
+    return out
+
+
+@pytest.mark.parametrize("m,r", [(1, 0.5), (5, 0.5), (15, 0.5), (15, 0.0), (4, 2.0)])
+def test_min_pair_disks_datum_brute_force(m, r):
+    rng = np.random.default_rng(100 + m)
+    pb = model.Problem(n=3 * m, ham="dubins_pairs", datum="min_pair_disks", datum_p=(r,), nu=0.01)
+    y = np.concatenate([rng.uniform(-3, 3, (300, 3 * m)), rng.normal(0, 0.05, (20, 3 * m))])
+    y[:, 2::3] = rng.uniform(-50, 50, (len(y), m))          # headings do not enter the datum
+    np.testing.assert_allclose(model.datum(pb, y[:, None, :])[:, 0], _min_pair_disks_brute(y, r), rtol=0,
+                               atol=1e-14)
+    # the [Q, N, n] layout used by the estimator gives the same values
+    np.testing.assert_array_equal(model.datum(pb, y.reshape(16, 20, 3 * m)).ravel(),
+                                  model.datum(pb, y[:, None, :])[:, 0])
+
+
+@pytest.mark.parametrize("m", [1, 3, 15])
+def test_min_pair_disks_gradient_central_differences(m):
+    rng = np.random.default_rng(200 + m)
+    pb = model.Problem(n=3 * m, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01)
+    x = rng.uniform(-3, 3, (40, 3 * m))
+    g = model.datum_grad(pb, x)
+    h = 1e-6
+    for q in range(len(x)):
+        rho = np.hypot(x[q, 0::3], x[q, 1::3])
+        srt = np.sort(rho)
+        if m > 1 and srt[1] - srt[0] < 1e-3:
+            continue                                      # too close to a tie for a difference quotient
+        for d in range(3 * m):
+            e = np.zeros(3 * m)
+            e[d] = h
+            fd = (_min_pair_disks_brute((x[q] + e)[None], 0.5) - _min_pair_disks_brute((x[q] - e)[None], 0.5))[0]
+            assert abs(fd / (2 * h) - g[q, d]) < 1e-6, (q, d)
+        assert abs(np.linalg.norm(g[q]) - 1.0) < 1e-12         # a distance: unit gradient off the kinks
+
+
+def test_min_pair_disks_gradient_ties_and_centre():
+    pb = model.Problem(n=9, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01)
+    x = np.array([
+        [3.0, 0.0, 0.1, 1.0, 0.0, 0.2, 0.0, 1.0, 0.3],      # pairs 1 and 2 tie at distance 1: pair 1 wins
+        [0.6, 0.8, 0.0, 0.8, 0.6, 0.0, 1.0, 0.0, 0.0],      # all three tie: pair 0 wins
+        [2.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 2.0],      # pairs 1 and 2 at the centre: 0 (kink rule)
+    ])
+    g = model.datum_grad(pb, x)
+    np.testing.assert_array_equal(g[0], [0, 0, 0, 1.0, 0, 0, 0, 0, 0])
+    np.testing.assert_allclose(g[1], [0.6, 0.8, 0, 0, 0, 0, 0, 0, 0], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(g[2], np.zeros(9))
+    np.testing.assert_allclose(model.datum(pb, x[:, None, :])[:, 0], [0.5, 0.5, -0.5], rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------- the general coefficient branch
+def test_general_coefficient_branch_exact_case():
+    """H = |p|^2/2 through the general branch with eta = 0 and no clipping is
+    exactly 1/delta: the exact reduction the coefficient definition is built
+    to reproduce.  A wrong factor (1/delta, |p| for |p|^2) fails here."""
+    rng = np.random.default_rng(7)
+    for nu in (0.01, 0.05, 0.3):
+        p = rng.normal(size=(500, 6)) * rng.uniform(0.1, 10, (500, 1))
+        H = 0.5 * np.sum(p * p, axis=1)
+        c = model.frozen_coefficient(H, p, 2 * nu, eta=0.0, c_min=0.0, c_max=np.inf)
+        np.testing.assert_allclose(c, 1.0 / (2 * nu), rtol=4e-16, atol=0)
+    # the regularised denominator: eta = |p|^2 halves it
+    p = np.array([[3.0, 4.0]])
+    c = model.frozen_coefficient(np.array([12.5]), p, 0.1, eta=25.0, c_min=0.0, c_max=np.inf)
+    assert c[0] == pytest.approx(5.0, rel=1e-15)
+
+
+def test_general_coefficient_clip_keeps_sign():
+    p = np.ones((5, 2))
+    H = np.array([1e9, -1e9, 1e-12, -1e-12, 0.0])
+    c = model.frozen_coefficient(H, p, 0.02, eta=0.0, c_min=0.5, c_max=20.0)
+    np.testing.assert_array_equal(c, [20.0, -20.0, 0.5, -0.5, 0.5])
+
+
+def test_dubins_coefficient_hand_values():
+    """One Dubins pair worked by hand (nu = 0.01, so 2/delta = 100; eta = 0.01).
+
+    x = (0, 2, pi/2), p = (1, 0.5, 0.25), unit speeds and turn bound:
+      H = p1 (cos x3 - 1) + p2 sin x3 + |p1 x2 - p2 x1 - p3| - |p3|
+        = -1 + 0.5 + 1.75 - 0.25 = 1,     |p|^2 + eta = 1.3225,  c = 100 / 1.3225.
+    p = (1, -2, 0): H = -1 - 2 + 2 - 0 = -1,  |p|^2 + eta = 5.01,  c = -100 / 5.01;
+    with the printed sign of the p2 term (s = -1): H = -1 + 2 + 2 = 3, c = 300 / 5.01;
+    with the tube coefficient min{0, H}: H = 0 there, so c = +c_min.
+    """
+    x = np.array([[0.0, 2.0, np.pi / 2]] * 2)
+    p = np.array([[1.0, 0.5, 0.25], [1.0, -2.0, 0.0]])
+    kw = dict(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01, eta=0.01)
+    c = model.coefficient(model.Problem(ham_p=(1.0, 1.0, 1.0, 1.0), **kw), x, p)
+    np.testing.assert_allclose(c, [100 / 1.3225, -100 / 5.01], rtol=1e-14)
+    c = model.coefficient(model.Problem(ham_p=(-1.0, 1.0, 1.0, 1.0), **kw), x, p)
+    np.testing.assert_allclose(c[1], 300 / 5.01, rtol=1e-14)
+    c = model.coefficient(model.Problem(ham_p=(-1.0, 1.0, 1.0, 1.0), tube=True, **kw), x, p)
+    assert c[1] == model.Problem(**kw).c_min
+
+
+# ------------------------------------------------- warm start of the Picard loop
+def test_picard_warm_start_value():
+    """The "Fix" step with a given v^(0): v0 = l(x) is the plain start; a v0
+    that is already the first iterate of a p-independent problem (H = |p|^2/2,
+    no shift) gives a zero first residual and no flags; any other v0 changes
+    only the first residual."""
+    pb = model.Problem(n=2, ham="quadratic", datum="ball", datum_p=(2, 1.0), nu=0.05, seed=3)
+    x = np.random.default_rng(5).uniform(-2, 2, (32, 2))
+    base = estimator.picard(pb, x, 0.5, 2048, K=3)
+    same = estimator.picard(pb, x, 0.5, 2048, K=3, v0=estimator.datum_at(pb, x))
+    np.testing.assert_array_equal(same.v, base.v)
+    np.testing.assert_array_equal(same.resid_hist, base.resid_hist)
+    first = estimator.picard(pb, x, 0.5, 2048, K=1)
+    warm = estimator.picard(pb, x, 0.5, 2048, K=2, tol=1e-12, v0=first.v)
+    assert warm.resid_hist[0] == 0.0 and warm.iters_done == 1 and not warm.flags.any()
+    v0 = estimator.datum_at(pb, x) + 1.0
+    other = estimator.picard(pb, x, 0.5, 2048, K=3, v0=v0)
+    np.testing.assert_array_equal(other.v, base.v)
+    np.testing.assert_array_equal(other.resid_hist[1:], base.resid_hist[1:])
+    assert other.resid_hist[0] == pytest.approx(np.linalg.norm(first.v - v0) / np.linalg.norm(v0), rel=1e-14)
+
+
+def test_picard_nan_warm_start_is_flagged():
+    """A non-finite relative change is not within tolerance: every state with
+    a NaN start is flagged and the loop does not stop early on a NaN residual."""
+    pb = model.Problem(n=3, ham="dubins_pairs", datum="min_pair_disks", datum_p=(0.5,), nu=0.01, tilt=True,
+                       seed=4)
+    x = np.random.default_rng(9).uniform(-3, 3, (16, 3))
+    v0 = np.zeros(16)
+    v0[[2, 7]] = np.nan
+    res = estimator.picard(pb, x, 1.0, 1024, K=1, tol=1e-3, v0=v0)
+    assert res.flags[2] and res.flags[7]
+    assert np.isnan(res.resid_hist[0])
+    res = estimator.picard(pb, x, 1.0, 1024, K=3, tol=1e-3, v0=v0)
+    assert res.iters_done == 3 or res.resid_hist[-1] < 1e-3
