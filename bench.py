@@ -763,6 +763,19 @@ def murmuration_study(ctx, stream):
             "paper_seconds_whole_study_8_cpu_cores": 429.0}
 
 
+def cpu_model_name() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or the platform's description."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_oracle_baseline(w, per_worker: int, workers: int):
     """Time the FP64 oracle (unchanged) on workers x per_worker queries of the workload."""
     import concurrent.futures as cf
@@ -837,6 +850,7 @@ def main():
         workers = min(16, os.cpu_count() or 1)
         rate, dt, pairs = cpu_oracle_baseline(w, args.cpu_queries_per_worker, workers)
         cpu = {"value": rate, "unit": "query·samples/s", "cores": workers, "kind": "oracle",
+               "cpu_model": cpu_model_name(),
                "sample": f"{workers * args.cpu_queries_per_worker} queries x N={w.N} x K={w.K} of the same "
                          f"workload ({pairs:.3g} pairs, {dt:.1f} s, one process per core)"}
         print(f"cpu baseline: {rate:.3e} pairs/s on {workers} cores ({dt:.1f} s)", file=sys.stderr, flush=True)

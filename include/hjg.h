@@ -40,7 +40,12 @@
  *    reproducible bit for bit from (seed, problem_id, time_step, iteration,
  *    query).
  *  - Not thread-safe per context: calls that share an hjg_ctx must be
- *    serialised by the caller.
+ *    serialised by the caller, and run on one stream (or be ordered between
+ *    streams by the caller): they share the context's workspace.
+ *  - Non-finite outputs are reported, not passed on silently: every entry
+ *    point that synchronises checks its outputs and returns HJG_ENONFINITE
+ *    (outputs written, but some are NaN or infinite) where one is not finite;
+ *    a fully asynchronous call leaves that check to the caller.
  *  - Environment switches, read per call, select alternative paths for
  *    comparison (the defaults are the tuned ones): HJG_NO_MFMA=1,
  *    HJG_TARGET_BLOCKS=n, HJG_NO_GRAPH=1, HJG_BATCH_SPLIT=n,
@@ -224,14 +229,19 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
  *   c_out     device [Q] out: coefficient frozen in the last executed iteration,
  *             or NULL
  *   ess       device [Q] out, or NULL
- *   flags     device uint8 [Q] out: per-state relative change
- *             |dv| / max(|v^(k)|, 1e-2 sigma sqrt(n)) > tol at the last
- *             executed iteration, or NULL
+ *   flags     device uint8 [Q] out: 1 where the per-state relative change
+ *             |dv| / max(|v^(k)|, 1e-2 sigma sqrt(n)) is not <= tol (a NaN
+ *             change is flagged), or v or Dv is not finite, at the last
+ *             executed iteration; or NULL
  *   resid_hist host double [K] out: relative change per iteration (entries
  *             after the stop are set to 0), or NULL
  *   iters_done host out: number of executed iterations, or NULL
- * Synchronises the stream when resid_hist or iters_done is given or tol > 0.
- * Returns HJG_ENOTCONVERGED (outputs valid) when tol > 0 was not reached.
+ * Synchronises the stream when resid_hist or iters_done is given or tol > 0;
+ * such a call returns HJG_ENONFINITE when v or Dv of some state is not finite
+ * after the last executed iteration (counted on the device in the residual
+ * reduction), else HJG_ENOTCONVERGED (outputs valid) when tol > 0 was not
+ * reached.  A call with neither host output nor tol > 0 is fully
+ * asynchronous and reports no non-finite output.
  */
 int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
                      const float* x, double t, int32_t N, int32_t K, double tol,
@@ -257,7 +267,10 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
  * loop over levels is recorded once into a HIP graph (problems with K[p] <= k
  * drop out of level k; each has its own device stop flag).  resid_hist (host
  * [P][max K], entries past K[p] zero) and iters (host [P]) are optional;
- * giving either synchronises the stream.
+ * giving either synchronises the stream, and such a call returns
+ * HJG_ENONFINITE when some state of some problem ends with a non-finite value
+ * or gradient.  A call whose batch differs from the previous call's waits for
+ * that call's replay (on whatever stream it ran) before it re-plans.
  */
 int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problems,
                              const int64_t* q_off, const int32_t* N, const int32_t* K,
@@ -402,7 +415,10 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x,
  *   3. the flagged states are compacted and solved again by the plain sweep
  *      (no warm start) with N_fb draws and K_fb iterations, and scattered back.
  * v, grad device out; fell_back device uint8 [Q] out (1 where step 3 ran);
- * *n_fallback (host) the number of such states.  Synchronises the stream. */
+ * *n_fallback (host) the number of such states.  A state whose step-2 result
+ * is not finite (a non-finite surrogate output, say) is flagged and falls
+ * back.  Synchronises the stream; returns HJG_ENONFINITE if a value or
+ * gradient is still not finite after step 3. */
 int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* problem,
                         int64_t Q, const float* x, double t, int32_t N_s,
                         int32_t K_s, int32_t N_fb, int32_t K_fb, double tol,
@@ -428,7 +444,8 @@ int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* probl
  * *iters_done host or NULL.  problem->n must equal the surrogate's n.
  * Synchronises the stream after every iteration (the stop test is read on the
  * host).  Errors: HJG_EINVAL (arguments), HJG_EUNSUPPORTED (fresh draws),
- * HJG_ENOMEM, HJG_EHIP. */
+ * HJG_ENOMEM, HJG_EHIP, HJG_ENONFINITE (some state ends with a non-finite
+ * value or gradient; outputs written). */
 int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* problem,
                             int64_t Q, const float* x, double t_prev, double dt,
                             int32_t N, int32_t K, double tol, uint32_t time_step,

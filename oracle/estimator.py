@@ -123,11 +123,12 @@ class PicardResult:
     c: np.ndarray            # coefficient frozen in the last executed iteration
     ess: np.ndarray
     flags: np.ndarray        # per-query relative change not <= tol at the last iteration
-                             # (a NaN change is flagged)
+                             # (a NaN change is flagged), or a non-finite v or gradient
     resid_hist: np.ndarray   # global relative L2 change per executed iteration
     iters_done: int
     lmax: np.ndarray
     theta: np.ndarray        # shift used in the last executed iteration
+    rq: np.ndarray           # per-query relative change of the last executed iteration
 
 
 def v_floor(pb: model.Problem, t: float) -> float:
@@ -165,7 +166,14 @@ def picard(pb: model.Problem, x: np.ndarray, t: float, N: int, K: int, tol: floa
         p = est.grad
         if r < tol:
             break
-    return PicardResult(est.v, est.grad, c, est.ess, ~(rq <= tol), np.array(hist), len(hist), est.lmax, theta)
+    return PicardResult(est.v, est.grad, c, est.ess, _flags(rq, tol, est), np.array(hist), len(hist), est.lmax,
+                        theta, rq)
+
+
+def _flags(rq: np.ndarray, tol: float, est: Estimate) -> np.ndarray:
+    """Not converged: the relative change is not within tol (NaN included) or
+    the estimate itself is not finite."""
+    return ~(rq <= tol) | ~np.isfinite(est.v) | ~np.all(np.isfinite(est.grad), axis=1)
 
 
 def datum_at(pb: model.Problem, x: np.ndarray) -> np.ndarray:
@@ -212,4 +220,5 @@ def tube_step(pb: model.Problem, x: np.ndarray, t_prev: float, dt: float, N: int
         p = est.grad
         if r < tol:
             break
-    return PicardResult(est.v, est.grad, c, est.ess, ~(rq <= tol), np.array(hist), len(hist), est.lmax, theta)
+    return PicardResult(est.v, est.grad, c, est.ess, _flags(rq, tol, est), np.array(hist), len(hist), est.lmax,
+                        theta, rq)

@@ -111,3 +111,37 @@ def value_grad_at(params, norm, x, t):
     xt = np.concatenate([x, np.full((x.shape[0], 1), float(t))], axis=1)
     out = forward_bf16_storage(params, (xt - norm[0]) / norm[1]) * norm[3] + norm[2]
     return out[:, 0], out[:, 1:]
+
+
+def loss_and_grads_bf16_storage(params, X, T, lam: float, rnd=round_bf16):
+    """loss_and_grads with the storage rounding of a bfloat16 network.
+
+    What a network whose matrix operands live in bfloat16 computes, with every
+    product and sum in float64: weights, inputs and hidden activations rounded
+    (as in forward_bf16_storage); the output error dY = 2 w (Y - T) / B and
+    each back-propagated error dz = (dY W) silu'(z) rounded before they enter
+    a product; the output layer, the loss and the parameter gradients not
+    rounded.  rnd = identity gives loss_and_grads exactly.
+    """
+    B, nout = T.shape
+    n = nout - 1
+    wts = np.full(nout, lam / n)
+    wts[0] = 1.0
+    Wr = [rnd(W) for W, _ in params]
+    acts, pre = [rnd(X)], []
+    h = acts[0]
+    L = len(params)
+    for li, (_, b) in enumerate(params):
+        z = h @ Wr[li].T + b
+        pre.append(z)
+        h = rnd(silu(z)) if li < L - 1 else z
+        acts.append(h)
+    diff = h - T
+    loss = np.sum(wts * diff * diff) / B
+    d = rnd(2.0 * wts * diff / B)
+    grads = [None] * L
+    for li in range(L - 1, -1, -1):
+        grads[li] = (d.T @ acts[li], d.sum(axis=0))
+        if li > 0:
+            d = rnd((d @ Wr[li]) * dsilu(pre[li - 1]))
+    return loss, grads

@@ -83,6 +83,7 @@ struct hjg_ctx {
     DevBuf ws, args, items;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t replay_ev = nullptr;             // recorded after each replay
     std::vector<int64_t> resid_off, ctrl_off;   // per problem, bytes into ws
     std::vector<int> K;
   } batch;
@@ -90,6 +91,11 @@ struct hjg_ctx {
 
 namespace {
 constexpr int kMaxTimed = 256;
+// Device control words of a context (ctx->ctrl): 0 Picard stop flag, 1
+// executed iterations, 2 finiteness flag of hjg_value_grad, 3 that of the
+// flock search, 4 Picard count of states with a non-finite output.
+constexpr int kCtrlWords = 8;
+constexpr int kCtrlNonfinite = 4;
 }
 
 namespace {
@@ -463,6 +469,7 @@ void hjg_ctx_destroy(hjg_ctx* ctx) {
     if (ctx->join_ev[j]) (void)hipEventDestroy(ctx->join_ev[j]);
   }
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->batch.replay_ev) (void)hipEventDestroy(ctx->batch.replay_ev);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
 }
@@ -564,7 +571,7 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
   HJG_HIP(launch_finalize(f, s));
 
   if (check_finite) {
-    if ((rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int)))) return rc;
+    if ((rc = ensure(ctx, ctx->ctrl, kCtrlWords * sizeof(int)))) return rc;
     int* flag = (int*)ctx->ctrl.p + 2;
     HJG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     HJG_HIP(launch_finite_check(v, Q, flag, s));
@@ -627,6 +634,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
   const int nblocks = (int)div_up(Q, kThreads);
   int* done = (int*)ctx->ctrl.p;
   int* iters = done + 1;
+  int* nonfinite = done + kCtrlNonfinite;
   float* th = p->tilt ? (float*)ctx->thwork.p : nullptr;
 
   InitArgs in{};
@@ -646,6 +654,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
   in.th = th;
   in.done = done;
   in.iters = iters;
+  in.nonfinite = nonfinite;
   in.resid = (double*)ctx->resid.p;
   HJG_HIP(launch_init(in, s));
 
@@ -712,6 +721,7 @@ int record_picard(hjg_ctx* ctx, const PicardKey& k, hipStream_t s) {
     r.resid = (double*)ctx->resid.p;
     r.done = done;
     r.iters = iters;
+    r.nonfinite = nonfinite;
     HJG_HIP(launch_reduce(r, s));
   }
   return HJG_OK;
@@ -745,9 +755,9 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   if ((rc = ensure(ctx, ctx->vprev, Q * sizeof(float)))) return rc;
   if ((rc = ensure(ctx, ctx->cwork, Q * sizeof(float)))) return rc;
   if (p->tilt && (rc = ensure(ctx, ctx->thwork, (size_t)Q * p->n * sizeof(float)))) return rc;
-  if ((rc = ensure(ctx, ctx->blockpart, (size_t)div_up(Q, kThreads) * 2 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->blockpart, (size_t)div_up(Q, kThreads) * 3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->resid, 256 * sizeof(double)))) return rc;
-  if ((rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int)))) return rc;
+  if ((rc = ensure(ctx, ctx->ctrl, kCtrlWords * sizeof(int)))) return rc;
   if (!fresh && (rc = ensure_table(ctx, p, N, step, p->grad_cv != 0, s))) return rc;
 
   PicardKey key;
@@ -816,11 +826,15 @@ int hjg_picard_sweep(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float*
   }
 
   if (resid_hist || iters_done || tol > 0) {
-    int ctrl[2] = {0, 0};
-    HJG_HIP(hipMemcpyAsync(ctrl, ctx->ctrl.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    int ctrl[kCtrlWords] = {};
+    HJG_HIP(hipMemcpyAsync(ctrl, ctx->ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, s));
     if (resid_hist) HJG_HIP(hipMemcpyAsync(resid_hist, ctx->resid.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
     HJG_HIP(hipStreamSynchronize(s));
     if (iters_done) *iters_done = ctrl[1];
+    if (ctrl[kCtrlNonfinite])
+      return fail(HJG_ENONFINITE, std::to_string(ctrl[kCtrlNonfinite]) + " of " + std::to_string(Q) +
+                                      " states have a non-finite value or gradient after iteration " +
+                                      std::to_string(ctrl[1]));
     if (tol > 0 && !ctrl[0]) {
       g_err = "tolerance not reached within K iterations";
       return HJG_ENOTCONVERGED;
@@ -964,6 +978,10 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
   put(&mode, sizeof(mode));
 
   if (key != B.key || !B.exec) {
+    // a replay of the previous plan may still run on some stream: it reads
+    // the buffers rewritten below
+    if (!B.replay_ev) HJG_HIP(hipEventCreateWithFlags(&B.replay_ev, hipEventDisableTiming));
+    else HJG_HIP(hipEventSynchronize(B.replay_ev));
     drop_batch_graph(ctx);
     // ---- per-problem plan and workspace carving
     struct Plan1 {
@@ -999,7 +1017,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       q.o_vp = take(q.Q * 4);
       q.o_c = take(q.Q * 4);
       q.o_th = pr.tilt ? take(q.Q * pr.n * 4) : -1;
-      q.o_bp = take(q.qb256 * 16);
+      q.o_bp = take(q.qb256 * 24);
       q.o_res = take(Ks[p] * 8);
       q.o_ctrl = take(16);
       q.o_tab = take((int64_t)pr.n * q.tstride * (q.bf16 ? 2 : 4));
@@ -1089,6 +1107,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       I.th = th;
       I.done = done;
       I.iters = done + 1;
+      I.nonfinite = done + 2;
       I.resid = (double*)at(q.o_res);
       ReduceArgs& R = ra[p];
       R = ReduceArgs{};
@@ -1098,6 +1117,7 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
       R.resid = I.resid;
       R.done = done;
       R.iters = done + 1;
+      R.nonfinite = done + 2;
       B.resid_off[p] = q.o_res;
       B.ctrl_off[p] = q.o_ctrl;
     }
@@ -1304,19 +1324,29 @@ extern "C" int hjg_picard_sweep_batched(hjg_ctx* ctx, int32_t P, const hjg_probl
     B.key = key;
   }
   HJG_HIP(hipGraphLaunch(B.exec, s));
+  // the next call that re-plans waits for this replay before it rewrites the
+  // workspace, argument records and work items the replay reads
+  HJG_HIP(hipEventRecord(B.replay_ev, s));
   if (resid_hist || iters) {
     std::vector<double> r;
+    int64_t bad_states = 0;
+    int first_bad = -1;
     for (int p = 0; p < P; ++p) {
       r.assign(B.K[p], 0.0);
-      int ctrl[2] = {0, 0};
+      int ctrl[3] = {0, 0, 0};
       HJG_HIP(hipMemcpyAsync(r.data(), (char*)B.ws.p + B.resid_off[p], B.K[p] * sizeof(double),
                              hipMemcpyDeviceToHost, s));
-      HJG_HIP(hipMemcpyAsync(ctrl, (char*)B.ws.p + B.ctrl_off[p], 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HJG_HIP(hipMemcpyAsync(ctrl, (char*)B.ws.p + B.ctrl_off[p], 3 * sizeof(int), hipMemcpyDeviceToHost, s));
       HJG_HIP(hipStreamSynchronize(s));
       if (resid_hist)
         for (int k = 0; k < Kmax; ++k) resid_hist[(int64_t)p * Kmax + k] = k < B.K[p] ? r[k] : 0.0;
       if (iters) iters[p] = ctrl[1];
+      if (ctrl[2] && first_bad < 0) first_bad = p;
+      bad_states += ctrl[2];
     }
+    if (bad_states)
+      return fail(HJG_ENONFINITE, std::to_string(bad_states) + " states have a non-finite value or gradient "
+                                  "(first in problem " + std::to_string(first_bad) + ")");
   }
   return HJG_OK;
 }
@@ -1353,7 +1383,7 @@ extern "C" int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const flo
   const int64_t nb = (cells + 1 + 4095) / 4096;
   if ((rc = ensure(ctx, ctx->g_cell, M * sizeof(int))) || (rc = ensure(ctx, ctx->g_rank, M * sizeof(int))) ||
       (rc = ensure(ctx, ctx->g_start, (cells + 1) * sizeof(int))) || (rc = ensure(ctx, ctx->g_bsum, nb * sizeof(int))) ||
-      (rc = ensure(ctx, ctx->g_sorted, M * sizeof(float4))) || (rc = ensure(ctx, ctx->ctrl, 4 * sizeof(int))))
+      (rc = ensure(ctx, ctx->g_sorted, M * sizeof(float4))) || (rc = ensure(ctx, ctx->ctrl, kCtrlWords * sizeof(int))))
     return rc;
   // positions must be finite: the cell of a NaN is not defined
   int* flag = (int*)ctx->ctrl.p + 3;

@@ -72,7 +72,8 @@ struct FinalizeArgs {
   uint8_t* flags;        // [Q] or nullptr
   float tol;
   float vfloor;
-  double* blockpart;     // [gridDim.x][2]: sum dv^2, sum vprev^2
+  double* blockpart;     // [gridDim.x][3]: sum dv^2, sum vprev^2, number of states
+                         // whose v or gradient is not finite
   float* c_next;         // [Q] (may alias c)
   float* th_next;        // [n][Q] (may alias theta) or nullptr
   HamP hp;
@@ -96,6 +97,7 @@ struct InitArgs {
   float* th;             // or nullptr
   int* done;
   int* iters;
+  int* nonfinite;        // reset to 0 (or nullptr)
   double* resid;         // [K]
 };
 
@@ -107,6 +109,7 @@ struct ReduceArgs {
   double* resid;
   int* done;
   int* iters;
+  int* nonfinite;        // out: states of iteration k with a non-finite v or gradient (or nullptr)
 };
 
 // A batched launch: block b serves items[b] = (problem, query block, split)

@@ -100,7 +100,11 @@ template <int NM>
 __device__ __forceinline__ void init_block(const InitArgs& I, int64_t qblock) {
   if (qblock == 0) {
     for (int k = threadIdx.x; k < I.K; k += kThreads) I.resid[k] = 0.0;
-    if (threadIdx.x == 0) { *I.done = 0; *I.iters = 0; }
+    if (threadIdx.x == 0) {
+      *I.done = 0;
+      *I.iters = 0;
+      if (I.nonfinite) *I.nonfinite = 0;
+    }
   }
   const int64_t q = qblock * kThreads + threadIdx.x;
   if (q >= I.Q) return;
@@ -148,7 +152,7 @@ template <int NM, bool MERGE>
 __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qblock) {
   const int64_t q = qblock * kThreads + threadIdx.x;
   const bool active = q < F.Q;
-  double dv2 = 0.0, vp2 = 0.0;
+  double dv2 = 0.0, vp2 = 0.0, bad = 0.0;
   if (active) {
     const int64_t Q = F.Q;
     // One pass over the splits: each split's rescale factor is formed once
@@ -201,6 +205,7 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
     const double sg = (double)F.sigma;
     const double v = -(M * kLn2 + log(S / (double)F.N)) / c;
     float xq[NM], pg[NM];
+    bool finite = isfinite(v);
 #pragma unroll
     for (int d = 0; d < NM; ++d) {
       xq[d] = 0.f;
@@ -222,10 +227,12 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
         if (F.cv) gbar -= zsum ? zs / (double)F.N : F.zbar_tab[d];
         const double gr = -(th + sg * gbar) / (c * sg * sg);
         pg[d] = (float)gr;
+        finite = finite && isfinite(pg[d]);
         F.grad[(int64_t)d * Q + q] = pg[d];
       }
     }
     const float vf = (float)v;
+    finite = finite && isfinite(vf);
     F.v[q] = vf;
     if (F.ess) F.ess[q] = (float)(S * S / S2);
     if (F.picard) {
@@ -233,7 +240,10 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
       const float dv = vf - vp;
       dv2 = (double)dv * (double)dv;
       vp2 = (double)vp * (double)vp;
-      if (F.flags) F.flags[q] = (fabsf(dv) / fmaxf(fabsf(vp), F.vfloor)) > F.tol ? 1 : 0;
+      bad = finite ? 0.0 : 1.0;
+      // a relative change that is not <= tol (NaN included), or a non-finite
+      // output, is not converged
+      if (F.flags) F.flags[q] = (!((fabsf(dv) / fmaxf(fabsf(vp), F.vfloor)) <= F.tol) || !finite) ? 1 : 0;
       F.vprev[q] = vf;
       if (F.c_out) F.c_out[q] = F.c[q];
       const float cn = coefficient<NM>(F.hp, xq, pg);
@@ -249,16 +259,18 @@ __device__ __forceinline__ void finalize_block(const FinalizeArgs& F, int64_t qb
     for (int off = 32; off > 0; off >>= 1) {
       dv2 += __shfl_down(dv2, off, 64);
       vp2 += __shfl_down(vp2, off, 64);
+      bad += __shfl_down(bad, off, 64);
     }
-    __shared__ double red[2][kThreads / 64];
+    __shared__ double red[3][kThreads / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { red[0][wid] = dv2; red[1][wid] = vp2; }
+    if (lane == 0) { red[0][wid] = dv2; red[1][wid] = vp2; red[2][wid] = bad; }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < kThreads / 64; ++w) { a += red[0][w]; b += red[1][w]; }
-      F.blockpart[2 * qblock] = a;
-      F.blockpart[2 * qblock + 1] = b;
+      double a = 0.0, b = 0.0, c = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) { a += red[0][w]; b += red[1][w]; c += red[2][w]; }
+      F.blockpart[3 * qblock] = a;
+      F.blockpart[3 * qblock + 1] = b;
+      F.blockpart[3 * qblock + 2] = c;
     }
   }
 }
@@ -279,14 +291,23 @@ __global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const Finali
 
 // Relative L2 change over all queries from the block partials (float64, fixed order).
 __device__ __forceinline__ void reduce_block(const ReduceArgs& R) {
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < R.nblocks; i += kThreads) { a += R.blockpart[2 * i]; b += R.blockpart[2 * i + 1]; }
-  __shared__ double ra[kThreads], rb[kThreads];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < R.nblocks; i += kThreads) {
+    a += R.blockpart[3 * i];
+    b += R.blockpart[3 * i + 1];
+    c += R.blockpart[3 * i + 2];
+  }
+  __shared__ double ra[kThreads], rb[kThreads], rc[kThreads];
   ra[threadIdx.x] = a;
   rb[threadIdx.x] = b;
+  rc[threadIdx.x] = c;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) { ra[threadIdx.x] += ra[threadIdx.x + off]; rb[threadIdx.x] += rb[threadIdx.x + off]; }
+    if ((int)threadIdx.x < off) {
+      ra[threadIdx.x] += ra[threadIdx.x + off];
+      rb[threadIdx.x] += rb[threadIdx.x + off];
+      rc[threadIdx.x] += rc[threadIdx.x + off];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -294,6 +315,8 @@ __device__ __forceinline__ void reduce_block(const ReduceArgs& R) {
     const double r = den > 0.0 ? num / den : num;
     R.resid[R.k] = r;
     *R.iters = R.k + 1;
+    // the count of the last executed iteration is what the caller reads
+    if (R.nonfinite) *R.nonfinite = (int)rc[0];
     if (r < (double)R.tol) *R.done = 1;
   }
 }

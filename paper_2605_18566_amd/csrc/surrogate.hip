@@ -661,7 +661,9 @@ int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, in
   //    relative change of the last iteration decides the fallback
   rc = hjg_picard_sweep(ctx, p, Q, x, t, N_s, K_s, tol, time_step, (const float*)s->sg.p, (const float*)s->sv.p, v,
                         grad, nullptr, nullptr, fell_back, nullptr, nullptr, hip_stream);
-  if (rc < 0) return rc;
+  // non-finite states (a non-finite surrogate output, say) carry the flag
+  // and are solved again below; the final outputs are checked at the end
+  if (rc < 0 && rc != HJG_ENONFINITE) return rc;
   // 3. plain Monte Carlo (no warm start) on the flagged states
   int nb = 0;
   SG_HIP(launch_compact_count(fell_back, Q, (int*)s->bcount.p, &nb, st));
@@ -682,6 +684,14 @@ int hjg_surrogate_sweep(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p, in
     SG_HIP(launch_scatter_soa((const float*)s->vfb.p, 1, count, (const int*)s->index.p, Q, v, st));
     SG_HIP(launch_scatter_soa((const float*)s->gfb.p, n, count, (const int*)s->index.p, Q, grad, st));
   }
+  int* flag = (int*)s->total.p + 4;
+  int host = 0;
+  SG_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  SG_HIP(launch_finite_check(v, Q, flag, st));
+  SG_HIP(launch_finite_check(grad, Q * n, flag, st));
+  SG_HIP(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SG_HIP(hipStreamSynchronize(st));
+  if (host) return fail(HJG_ENONFINITE, "non-finite value or gradient after the plain fallback");
   return HJG_OK;
 }
 
@@ -724,7 +734,7 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
   if ((rc = grow(s->mt_table, (size_t)n * tstride * (bf16 ? 2 : 4))) || (rc = grow(s->mt_zbar, kMaxN * 8)) ||
       (rc = grow(s->mt_c, Q * 4)) || (rc = grow(s->mt_th, (size_t)Q * n * 4)) || (rc = grow(s->mt_vprev, Q * 4)) ||
       (rc = grow(s->mt_pm, Q * 4)) || (rc = grow(s->mt_pS, Q * 8)) || (rc = grow(s->mt_pS2, Q * 8)) ||
-      (rc = grow(s->mt_pG, (size_t)Q * n * 4)) || (rc = grow(s->mt_block, nblocks * 16)) ||
+      (rc = grow(s->mt_pG, (size_t)Q * n * 4)) || (rc = grow(s->mt_block, nblocks * 24)) ||
       (rc = grow(s->mt_resid, (size_t)K * 8)) || (rc = grow(s->mt_ctrl, 64)) || (rc = grow(s->tq, Q * 4)) ||
       (!fused && (rc = ensure_batch(s, Qc * N, false))))
     return rc;
@@ -740,6 +750,7 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
   const float sigma = (float)std::sqrt(2.0 * p->nu * dt);
   int* done = (int*)s->mt_ctrl.p;
   int* iters = done + 1;
+  int* nonfinite = done + 2;
   float* th = p->tilt ? (float*)s->mt_th.p : nullptr;
   hjg_problem pi = *p;              // the terminal datum is not used: a harmless one for init
   pi.datum = HJG_L_HALF_SQNORM;
@@ -761,6 +772,7 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
   in.th = th;
   in.done = done;
   in.iters = iters;
+  in.nonfinite = nonfinite;
   in.resid = (double*)s->mt_resid.p;
   SG_HIP(launch_init(in, st));
   const Partials part{(float*)s->mt_pm.p, (double*)s->mt_pS.p, (double*)s->mt_pS2.p, (float*)s->mt_pG.p, nullptr};
@@ -869,17 +881,20 @@ int hjg_surrogate_tube_step(hjg_ctx* ctx, hjg_surrogate* s, const hjg_problem* p
     r.resid = (double*)s->mt_resid.p;
     r.done = done;
     r.iters = iters;
+    r.nonfinite = nonfinite;
     SG_HIP(launch_reduce(r, st));
     int flag = 0;
     SG_HIP(hipMemcpyAsync(&flag, done, 4, hipMemcpyDeviceToHost, st));
     SG_HIP(hipStreamSynchronize(st));
     if (flag) break;
   }
-  int32_t nit = 0;
-  SG_HIP(hipMemcpyAsync(&nit, iters, 4, hipMemcpyDeviceToHost, st));
+  int32_t ctl[3] = {0, 0, 0};
+  SG_HIP(hipMemcpyAsync(ctl, done, sizeof(ctl), hipMemcpyDeviceToHost, st));
   if (resid_hist) SG_HIP(hipMemcpyAsync(resid_hist, s->mt_resid.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
   SG_HIP(hipStreamSynchronize(st));
-  if (iters_done) *iters_done = nit;
+  if (iters_done) *iters_done = ctl[1];
+  if (ctl[2])
+    return fail(HJG_ENONFINITE, std::to_string(ctl[2]) + " states have a non-finite value or gradient");
   return HJG_OK;
 }
 
