@@ -216,6 +216,32 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
                    void* hip_stream);
 
 /*
+ * hjg_value_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and the same results, bit for bit, as hjg_value_grad with
+ * check_finite = 0 (same sample-split plan and kernels), but the call
+ * allocates nothing and never synchronises: the sweep's scratch (split
+ * partial sums, the common table, its column means, the pair-coordinate
+ * copy) lives in one fixed device array of HJG_NOALLOC_SCRATCH_MIB MiB per
+ * GPU, part of the library's code object (each GPU the library runs on holds
+ * it until the process ends); its address is taken once per device by
+ * hjg_ctx_create.  The common table is generated on every call into that
+ * array (the context's table cache is not used), and every byte the kernels
+ * read is written earlier in the same call, so no clearing is needed.
+ * Returns HJG_EINVAL, before launching anything, when the call needs more
+ * scratch than the array holds (about Q * splits * (20 + 4n) bytes plus, for
+ * common draws, the table: the message gives the bytes needed).  Every call
+ * on one GPU shares that GPU's array and it keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other contexts on the same
+ * device, other host threads) race and give wrong results; order them.
+ */
+#define HJG_NOALLOC_SCRATCH_MIB 128
+int hjg_value_grad_noalloc(hjg_ctx* ctx, const hjg_problem* problem, int64_t Q,
+                           const float* x, double t, int32_t N, uint32_t time_step,
+                           uint32_t iter, const float* c, const float* theta,
+                           float* v, float* grad, float* ess, void* hip_stream);
+
+/*
  * Algorithm 1 at Q states and horizon t: v^(0) = l(x), p^(0) = D l(x) (or p0),
  * then for k = 0..K-1: c^(k) = coefficient(x, p^(k)), theta^(k) (if tilt),
  * one sweep -> v^(k+1), Dv^(k+1); p^(k+1) = Dv^(k+1).  Stops after iteration k

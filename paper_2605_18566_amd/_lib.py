@@ -93,6 +93,9 @@ SIGNATURES = [
     ("hjg_value_grad", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double, C.c_int32,
                                  C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hjg_value_grad_noalloc", C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_int64, C.c_void_p, C.c_double,
+                                         C.c_int32, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hjg_picard_sweep_batched", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_int64),
                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                            C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),

@@ -168,6 +168,32 @@ def value_grad(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: in
     return v, grad, ess
 
 
+def value_grad_noalloc(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N: int, c: torch.Tensor,
+                       theta: Optional[torch.Tensor] = None, time_step: int = 0, iteration: int = 0, out=None,
+                       stream=None):
+    """hjg_value_grad_noalloc: the sweep of value_grad with its scratch in the
+    library's fixed per-GPU array (the C call allocates nothing and does not
+    synchronise).  Pass out = (v, grad, ess) to allocate nothing here either."""
+    _require_cuda(x, "x")
+    n, Q = x.shape
+    if n != spec.n:
+        raise ValueError("x must have shape [n, Q]")
+    _require_cuda(c, "c")
+    if theta is not None:
+        _require_cuda(theta, "theta")
+    if out is None:
+        v = torch.empty(Q, dtype=torch.float32, device=x.device)
+        grad = torch.empty((n, Q), dtype=torch.float32, device=x.device)
+        ess = torch.empty(Q, dtype=torch.float32, device=x.device)
+    else:
+        v, grad, ess = out
+    p = spec.to_c()
+    check(_lib.lib().hjg_value_grad_noalloc(ctx.handle, C.byref(p), Q, _ptr(x), float(t), int(N), int(time_step),
+                                            int(iteration), _ptr(c), _ptr(theta), _ptr(v), _ptr(grad), _ptr(ess),
+                                            _stream(stream)))
+    return v, grad, ess
+
+
 @dataclass
 class PicardOut:
     v: torch.Tensor

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cstdlib>
 #include <cstring>
@@ -43,8 +44,20 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
 
+// Scratch of hjg_value_grad_noalloc: one fixed array per GPU (the code
+// object's copy on each device), never allocated or freed by the library.
+// Host code uses only the per-device address taken from hipGetSymbolAddress.
+namespace {
+constexpr size_t kNoallocScratchBytes = size_t(HJG_NOALLOC_SCRATCH_MIB) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
 struct hjg_ctx {
   int device = 0;
+  void* scratch = nullptr;     // this device's address of the no-allocation scratch
   hipStream_t cap = nullptr;   // stream used only to record graphs
   // side streams and events of a batched recording: the pair loops of one
   // Picard level become parallel graph branches
@@ -442,8 +455,24 @@ int hjg_ctx_create(int device, hjg_ctx** out) {
   HJG_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(HJG_EINVAL, "device index out of range");
   HJG_HIP(hipSetDevice(device));
+  if (device >= kMaxDevices) return fail(HJG_EINVAL, "device index above 63");
+  void* scr = nullptr;
+  {
+    // once per device, with that device current: the address of this
+    // device's copy of the scratch array
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(HJG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+      g_scratch_ptr[device] = p;
+    }
+    scr = g_scratch_ptr[device];
+  }
   hjg_ctx* ctx = new hjg_ctx();
   ctx->device = device;
+  ctx->scratch = scr;
   if (hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return fail(HJG_EHIP, "cannot create the graph-recording stream");
@@ -581,6 +610,99 @@ int hjg_value_grad(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x
     HJG_HIP(hipStreamSynchronize(s));
     if (host) return fail(HJG_ENONFINITE, "non-finite value in v or grad");
   }
+  return HJG_OK;
+}
+
+int hjg_value_grad_noalloc(hjg_ctx* ctx, const hjg_problem* p, int64_t Q, const float* x, double t, int32_t N,
+                           uint32_t step, uint32_t iter, const float* c, const float* theta, float* v, float* grad,
+                           float* ess, void* hip_stream) {
+  const hjg::detail::TraceRange trace_("hjg_value_grad_noalloc");
+  g_err.clear();
+  int rc = check_common(ctx, p, Q, t, N, step);
+  if (rc) return rc;
+  if (iter >= 256) return fail(HJG_EINVAL, "iter must be < 256");
+  if (Q == 0) return HJG_OK;
+  if (!x || !c || !v || !grad) return fail(HJG_EINVAL, "x, c, v and grad are required");
+  if (!ctx->scratch) return fail(HJG_EINVAL, "the context has no scratch address");
+  const bool fresh = p->sample_mode == HJG_S_FRESH;
+  const bool bf16 = p->sample_bf16 != 0;
+  const bool zdc = !fresh && pairs_kernel(p);
+  const auto tv = ctx->tuning.find(sweep_key(p, Q, N));
+  const Plan pl = plan_splits(Q, N, fresh, queries_per_block(p),
+                              tv == ctx->tuning.end() ? default_target_blocks(p) : tv->second, p->n);
+  // carve the scratch exactly as the allocating entry point sizes its buffers
+  const int64_t tstride = div_up(N, 64) * 64;
+  const int64_t sq = (int64_t)pl.splits * Q;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const int64_t o_m = take(sq * 4), o_S = take(sq * 8), o_S2 = take(sq * 8), o_G = take(sq * p->n * 4);
+  const int64_t o_Z = fresh && p->grad_cv ? take(sq * p->n * 4) : -1;
+  const int64_t o_tab = fresh ? -1 : take((int64_t)p->n * tstride * (bf16 ? 2 : 4));
+  const int64_t o_zd = zdc ? take((int64_t)N * pair_coord_stride(p->n / 3) * 4) : -1;
+  const int64_t o_zb = !fresh && p->grad_cv ? take(kMaxN * 8) : -1;
+  if (off > (int64_t)kNoallocScratchBytes)
+    return fail(HJG_EINVAL, "needs " + std::to_string(off) + " bytes of scratch, more than the " +
+                                std::to_string(kNoallocScratchBytes) + " available (reduce Q or N)");
+  char* base = (char*)ctx->scratch;
+  auto at = [&](int64_t o) -> void* { return o < 0 ? nullptr : (void*)(base + o); };
+  HJG_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!fresh) {
+    const uint32_t k0 = (uint32_t)(p->seed & 0xFFFFFFFFu), k1 = (uint32_t)(p->seed >> 32);
+    HJG_HIP(launch_table(p->n, tstride, tstride, k0, k1, make_tag(p->problem_id, step, 0), bf16, at(o_tab), s));
+    if (zdc)
+      HJG_HIP(launch_pair_coords(p->n / 3, N, tstride, at(o_tab), pair_coord_stride(p->n / 3), (float*)at(o_zd), s));
+    if (p->grad_cv) HJG_HIP(launch_zbar(p->n, N, tstride, bf16, at(o_tab), (double*)at(o_zb), s));
+  }
+  const float sigma = (float)std::sqrt(2.0 * p->nu * t);
+  const Partials part{(float*)at(o_m), (double*)at(o_S), (double*)at(o_S2), (float*)at(o_G), (float*)at(o_Z)};
+
+  SweepArgs a{};
+  a.n = p->n;
+  a.Q = Q;
+  a.N = N;
+  a.ns = pl.ns;
+  a.splits = pl.splits;
+  a.x = x;
+  a.c = c;
+  a.theta = theta;
+  a.sigma = sigma;
+  a.table = at(o_tab);
+  a.tstride = tstride;
+  a.zd = (const float*)at(o_zd);
+  a.dp = datum_params(p);
+  a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(p->seed >> 32);
+  a.tag = make_tag(p->problem_id, step, iter);
+  a.cv = p->grad_cv;
+  a.mfma = use_mfma(p);
+  a.part = part;
+  a.done = nullptr;
+  HJG_HIP(launch_sweep(a, fresh, bf16, s));
+
+  FinalizeArgs f{};
+  f.n = p->n;
+  f.Q = Q;
+  f.N = N;
+  f.splits = pl.splits;
+  f.sigma = sigma;
+  f.x = x;
+  f.c = c;
+  f.theta = theta;
+  f.part = part;
+  f.cv = p->grad_cv;
+  f.fresh = fresh;
+  f.zbar_tab = (const double*)at(o_zb);
+  f.v = v;
+  f.grad = grad;
+  f.ess = ess;
+  f.picard = 0;
+  f.hp = ham_params(p);
+  HJG_HIP(launch_finalize(f, s));
   return HJG_OK;
 }
 
