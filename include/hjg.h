@@ -85,8 +85,13 @@ enum hjg_ham {
                                 relative dynamics of the Dubins game in the
                                 appendix, s = -1 is the form printed there.      */
   HJG_H_ZERO = 2,            /* H = 0 (pure diffusion; c = +c_min)                     */
-  HJG_H_DOUBLE_INTEGRATOR = 3,/* n = 6, x = (pos, vel): <p_pos, vel> + u_max |p_vel|;
-                                ham_p = {u_max}                                       */
+  HJG_H_DOUBLE_INTEGRATOR = 3,/* n = 2k, k = 1, 2, 3, x = (pos[k], vel[k]), pos' = vel,
+                                vel' = u, |u| <= u_max: <p_pos, vel> + u_max |p_vel|
+                                (maximising control), or <p_pos, vel> - u_max |p_vel|
+                                when ham_p[1] < 0 (minimising control: at n = 2 the
+                                double integral plant of the appendix, eq. dint_ham
+                                with u = -sign(p2): p1 x2 - |p2|);
+                                ham_p = {u_max, s}                                    */
   HJG_H_PURSUIT_EVASION = 4, /* multi-pursuer single-evader game (Section 3.2): m = n/3
                                 planar agents (x, y, heading), the last the evader;
                                 sum_j a_j (p_xj cos th_j + p_yj sin th_j)

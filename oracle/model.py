@@ -27,7 +27,9 @@ class Problem:
     ham_p:   rockets: (a, g, u_max).  murmuration: (v_e, v_p, w_e, w_p,
              g_lo, g_hi).  quadratic/zero: unused.  dubins_pairs: (s, v_e, v_p, w) with s the
              sign of the p2 term (+1 from the relative dynamics, -1 for the form
-             the paper prints).  double_integrator: (u_max,).
+             the paper prints).  double_integrator: (u_max, s) for n = 2k,
+             k = 1..3 (positions, then velocities): s < 0 the control
+             minimises H (the paper's time-optimal plant), else it maximises.
              pursuit_evasion: (a_evader, a_pursuer, u_max) for m = n/3 planar
              agents (x, y, heading), the last one the evader.
     datum_p: ball: (k, r) -> ||y[:k]|| - r.  half_sqnorm: unused.
@@ -230,9 +232,15 @@ def hamiltonian(pb: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
         return (p1 * (ve - vp * np.cos(x4)) - p2 * vp * np.sin(x4) - wp * np.abs(p4)
                 + we * np.abs(p2 * x1 - p1 * x2 + p4) + glo * np.abs(p3) - ghi * np.abs(p3))
     if kind == "double_integrator":
-        # pos' = vel, vel' = u with ||u|| <= u_max, the agent maximising.
+        # pos' = vel, vel' = u with ||u|| <= u_max (k = n/2 axes): the control
+        # maximises <p, f> (+u_max ||p_vel||) or, with ham_p[1] < 0, minimises it
+        # (-u_max ||p_vel||; the double integral plant of the appendix, where
+        # u = -sign(p2) gives H = p1 x2 - |p2|)
+        k = pb.n // 2
         umax = float(pb.ham_p[0])
-        return np.sum(p[:, :3] * x[:, 3:6], axis=1) + umax * np.sqrt(np.sum(p[:, 3:6] ** 2, axis=1))
+        s = -1.0 if len(pb.ham_p) > 1 and float(pb.ham_p[1]) < 0 else 1.0
+        return (np.sum(p[:, :k] * x[:, k:2 * k], axis=1)
+                + s * umax * np.sqrt(np.sum(p[:, k:2 * k] ** 2, axis=1)))
     raise ValueError(f"unknown Hamiltonian {kind}")
 
 

@@ -193,8 +193,9 @@ int check_problem(const hjg_problem* p) {
       if (!(p->ham_p[2] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
       break;
     case HJG_H_DOUBLE_INTEGRATOR:
-      if (p->n != 6) return fail(HJG_EINVAL, "the double integrator needs n = 6");
+      if (p->n != 2 && p->n != 4 && p->n != 6) return fail(HJG_EINVAL, "the double integrator needs n = 2, 4 or 6");
       if (!(std::isfinite(p->ham_p[0]) && p->ham_p[0] >= 0)) return fail(HJG_EINVAL, "u_max must be >= 0");
+      if (!std::isfinite(p->ham_p[1])) return fail(HJG_EINVAL, "ham_p must be finite");
       break;
     default:
       return fail(HJG_EINVAL, "unknown Hamiltonian");

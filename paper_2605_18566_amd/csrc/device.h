@@ -229,8 +229,18 @@ __device__ inline float hamiltonian(const HamP& hp, const float* x, const float*
       return H;
     }
     case HJG_H_DOUBLE_INTEGRATOR: {
-      const float pv = sqrtf(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
-      return p[0] * x[3] + p[1] * x[4] + p[2] * x[5] + hp.p[0] * pv;
+      // n = 2k: positions x[0..k), velocities x[k..2k); the control term is
+      // +u_max |p_vel| (maximising control) or -u_max |p_vel| (ham_p[1] < 0)
+      const float um = hp.p[1] < 0.f ? -hp.p[0] : hp.p[0];
+      if (hp.n == 2) return p[0] * x[1] + um * fabsf(p[1]);
+      if constexpr (NM >= 4) {
+        if (hp.n == 4) return p[0] * x[2] + p[1] * x[3] + um * sqrtf(p[2] * p[2] + p[3] * p[3]);
+      }
+      if constexpr (NM >= 6) {
+        const float pv = sqrtf(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+        return p[0] * x[3] + p[1] * x[4] + p[2] * x[5] + um * pv;
+      }
+      return 0.f;
     }
     case HJG_H_MURMURATION: {
       const float ve = hp.p[0], vp = hp.p[1], we = hp.p[2], wp = hp.p[3], glo = hp.p[4], ghi = hp.p[5];

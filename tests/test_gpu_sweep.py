@@ -100,6 +100,9 @@ CASES = {
     # the two-rocket game (ball datum in (x, z)): fresh draws, and a common table with the shift
     "rockets_fresh": (dict(workloads.C7.problem_fields()), 700, 3001),
     "rockets_crn_tilt": (dict(workloads.C7.problem_fields(), sample_mode="crn_step", tilt=True), 500, 2048 + 3),
+    # the paper's double integral plant (minimising control, disc about the origin)
+    "dint_n2_fresh": (dict(workloads.C9.problem_fields()), 1000, 8000),
+    "dint_n2_crn_tilt": (dict(workloads.C9.problem_fields(), sample_mode="crn_step", tilt=True), 700, 3001),
 }
 
 
@@ -278,6 +281,39 @@ def test_picard_pursuit_game(ctx):
     assert bad.mean() <= 0.02
     assert np.all(dv[bad] <= 3 * se[bad])
     np.testing.assert_allclose(out.resid_hist, ref.resid_hist, rtol=5e-2, atol=1e-6)
+
+
+@pytest.mark.parametrize("tilt", [False, True], ids=["plain", "tilt"])
+def test_picard_double_integral_plant(ctx, tilt):
+    # the paper's double integral plant at its table's setting (N = 8,000 fresh
+    # draws, delta = 0.08, K = 15) on a 32 x 32 grid, horizon 0.8.  With the
+    # Laplace shift the proposal follows the gradient iterate, so a float32
+    # difference moves later proposals as well: that chain is compared over
+    # K = 5 (as the other shifted multi-iteration checks)
+    fields = dict(workloads.C9.problem_fields(), tilt=tilt)
+    Q, N, K, t = 1024, 8000, (5 if tilt else 15), 0.8
+    x = workloads.dint_grid(32).astype(np.float64)
+    pb = oracle_problem(fields)
+    from paper_2605_18566_amd import picard_sweep
+    ref = estimator.picard(pb, x, t, N, K, time_step=1)
+    out = picard_sweep(ctx, gpu_problem(fields), to_dev(soa(x)), t, N, K, time_step=1)
+    torch.cuda.synchronize()
+    sigma = np.sqrt(pb.delta * t)
+    v = out.v.cpu().numpy()
+    vt = 10 * value_tol(ref.v, ref.c, ref.theta, sigma, ref.lmax)
+    # fifteen iterations on fresh draws: a float32 difference in one iterate
+    # moves every later coefficient, and each iteration's estimate moves
+    # within its own band, so the band is 4 standard errors over 15
+    # iterations (3 over five)
+    se = (4 if K > 5 else 3) * np.sqrt(np.maximum(N / ref.ess - 1.0, 0.0) / N) / np.abs(ref.c)
+    dv = np.abs(v - ref.v)
+    print(f"[double integrator, tilt={tilt}] within 10 tol {np.mean(dv <= vt):.4f}, max |dv| {dv.max():.2e}, "
+          f"residuals {np.round(out.resid_hist[-3:], 4).tolist()} (oracle {np.round(ref.resid_hist[-3:], 4).tolist()})",
+          flush=True)
+    assert np.all(dv <= np.maximum(vt, se))
+    assert np.mean(dv <= vt) >= 0.98
+    np.testing.assert_allclose(out.resid_hist, ref.resid_hist, rtol=5e-2, atol=1e-6)
+    assert out.iters_done == K
 
 
 def test_picard_dubins_plain_h(ctx):

@@ -350,6 +350,32 @@ def test_double_integrator_hamiltonian_brute_force():
     assert abs(model.hamiltonian(pb, x[None], p[None])[0] - brute) < 1e-3
 
 
+def test_double_integral_plant_hamiltonian_brute_force():
+    """The double integral plant of the appendix: x1' = x2, x2' = u, |u| <= 1,
+    the Hamiltonian p1 x1' + p2 x2' minimised by the control (u = -sign p2):
+    H = p1 x2 - |p2|.  Brute force over a grid of admissible controls, also at
+    u_max = 0.5, and the planar (n = 4) form with a disc of controls."""
+    rng = np.random.default_rng(11)
+    for umax in (1.0, 0.5):
+        pb = model.Problem(n=2, ham="double_integrator", ham_p=(umax, -1.0), datum="ball", datum_p=(2, 0.2),
+                           nu=0.04)
+        u = np.linspace(-umax, umax, 2001)
+        for _ in range(20):
+            x, p = rng.standard_normal(2), rng.standard_normal(2)
+            brute = np.min(p[0] * x[1] + p[1] * u)
+            assert abs(model.hamiltonian(pb, x[None], p[None])[0] - brute) < 1e-12
+    # hand value: x = (0.3, -0.5), p = (2, -0.7): 2 * (-0.5) - 0.7 = -1.7
+    pb = model.Problem(n=2, ham="double_integrator", ham_p=(1.0, -1.0), datum="ball", datum_p=(2, 0.2), nu=0.04)
+    assert model.hamiltonian(pb, np.array([[0.3, -0.5]]), np.array([[2.0, -0.7]]))[0] == pytest.approx(-1.7, abs=1e-15)
+    pb4 = model.Problem(n=4, ham="double_integrator", ham_p=(1.0, -1.0), datum="ball", datum_p=(2, 0.2), nu=0.04)
+    ang = np.linspace(0, 2 * np.pi, 100001)
+    disc = np.stack([np.cos(ang), np.sin(ang)], 1)
+    for _ in range(10):
+        x, p = rng.standard_normal(4), rng.standard_normal(4)
+        brute = p[:2] @ x[2:] + np.min(disc @ p[2:])
+        assert abs(model.hamiltonian(pb4, x[None], p[None])[0] - brute) < 1e-8
+
+
 def test_rockets_hamiltonian_brute_force():
     # -max over u_e of min over u_p of <p, f(x, u_e, u_p)> on control grids
     # that contain the bang-bang corners, with the dynamics rows of the

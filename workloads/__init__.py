@@ -167,6 +167,27 @@ def rocket_slice(theta: float, m: int = 40) -> np.ndarray:
     return np.stack([X.ravel(), Z.ravel(), np.full(m * m, theta)], 1).astype(np.float32)
 
 
+# The paper's double integral plant (appendix; Table double_integrator_
+# convergence): x1' = x2, x2' = u, |u| <= 1, the control minimising
+# H = p1 x1' + p2 x2' (H = p1 x2 - |p2|); target the disc of radius 0.2 about
+# the origin (the paper gives no radius); delta = 0.08 (nu = 0.04), N = 8,000
+# fresh draws per state and iteration, K = 15, plain estimator (Algorithm 1);
+# evaluation on a 128 x 128 grid of [-1, 1]^2 (the range of the paper's
+# trajectory figure); the table's backward times t = 0.8, 0.5, 0.2, 0.0 are
+# read as the horizons 1 - t (a horizon of 0 would leave v = l exactly).
+DINT_TIMES = (0.8, 0.5, 0.2, 0.0)
+C9 = Workload("c9_double_integrator_n2", n=2, ham="double_integrator", ham_p=(1.0, -1.0), datum="ball",
+              datum_p=(2, 0.2), nu=0.04, t=1.0, Q=16384, N=8000, K=15, box=((-1.0, 1.0), (-1.0, 1.0)),
+              tilt=False, sample_mode="fresh", cfg=11)
+
+
+def dint_grid(m: int = 128) -> np.ndarray:
+    """States of an m x m grid of [-1, 1]^2 (cell centres), float32 [m*m, 2]."""
+    g = -1.0 + 2.0 * (np.arange(m) + 0.5) / m
+    X, V = np.meshgrid(g, g, indexing="ij")
+    return np.stack([X.ravel(), V.ravel()], 1).astype(np.float32)
+
+
 def horizons(w: Workload):
     """Time-to-go of each horizon: t_j = j T / S_t, j = 1..S_t."""
     return [w.T * (j + 1) / w.time_steps for j in range(w.time_steps)]
