@@ -9,7 +9,7 @@ from scipy import ndimage
 
 import workloads
 from oracle import estimator, model
-from tests._helpers import ess_rtol, gpu_problem, grad_tol, oracle_problem, soa, to_dev, value_tol
+from tests._helpers import ESS_RTOL_CAP, ess_rtol, gpu_problem, grad_tol, oracle_problem, soa, to_dev, value_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,9 @@ def test_one_sweep_matches_oracle(ctx, mode, tilt, Q, N):
     assert np.all(np.abs(v - ref.v) <= vt), f"value ratio {np.max(np.abs(v - ref.v) / vt):.2f}"
     assert np.all(np.linalg.norm(g - ref.grad, axis=1) <= grad_tol(ref.grad, c, sigma, N))
     et = ess_rtol(c, th if tilt else None, sigma, ref.lmax)
-    assert np.all(np.abs(ess - ref.ess) <= et * ref.ess)
+    held = et <= ESS_RTOL_CAP
+    assert held.mean() >= 0.6
+    assert np.all((np.abs(ess - ref.ess) <= et * ref.ess)[held])
 
 
 def test_picard_matches_oracle(ctx):
