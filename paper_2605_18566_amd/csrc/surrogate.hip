@@ -16,6 +16,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "mlp.h"
+#include "mlp_fused.h"
 
 using namespace hjg;
 
@@ -82,6 +83,8 @@ struct hjg_surrogate {
   Buf ctr;                          // training step counters (device)
   std::vector<Buf> Z, X, XT;
   Buf dZ[2], dZT[2];
+  std::vector<Buf> dZTl;            // fused step: transposed errors of each hidden layer [width][B]
+  Buf ticket;                       // fused step: blocks finished (zero between steps)
   // training set and sweep workspace
   Buf Xall, Tall, sv, sg, tq, flags, bcount, total, index, xfb, vfb, gfb;
   // time-marching step workspace
@@ -114,6 +117,9 @@ int ensure_batch(hjg_surrogate* s, int64_t rows, bool train) {
       if ((rc = grow(s->dZ[i], r * s->width * 2))) return rc;
       if ((rc = grow(s->dZT[i], r * s->width * 2))) return rc;
     }
+    s->dZTl.resize(s->depth);
+    for (int l = 0; l < s->depth; ++l)
+      if ((rc = grow(s->dZTl[l], r * s->width * 2))) return rc;
     if ((rc = grow(s->bl, (r * s->out_p / 256 + 2) * 8))) return rc;
     if ((rc = grow(s->acc, 64))) return rc;
   }
@@ -261,6 +267,77 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
   return HJG_OK;
 }
 
+// The fused training step (two launches: rows, then weight gradients with
+// AdamW) serves the network shapes its rows kernel is instantiated for, on
+// batches that are a multiple of 64 rows; HJG_MLP_FUSED=0 selects the
+// layer-by-layer launches instead.
+bool fused_ok(const hjg_surrogate* s, int64_t B) {
+  const char* e = std::getenv("HJG_MLP_FUSED");
+  if (e && e[0] == '0') return false;
+  return fused_rows_supported(s->width, s->in_p, s->out_p, s->depth) && B % 64 == 0;
+}
+
+FusedRowsArgs fused_rows_args(hjg_surrogate* s, int B, const __bf16* X, const float* T, const int* perm,
+                              const int64_t* batch) {
+  FusedRowsArgs a{};
+  const float* w = (const float*)s->w.p;
+  int k = 0;
+  for (int l = 0; l <= s->depth; ++l) {
+    FusedPhase& P = a.ph[k++];
+    P.W = (const __bf16*)s->Wb[l].p;
+    P.bias = w + s->boff[l];
+    P.outT = l < s->depth ? (__bf16*)s->XT[l].p : (__bf16*)s->dYT.p;
+  }
+  for (int l = s->depth; l >= 1; --l) {
+    FusedPhase& P = a.ph[k++];
+    P.W = (const __bf16*)s->WbT[l].p;
+    P.bias = nullptr;
+    P.outT = (__bf16*)s->dZTl[l - 1].p;
+  }
+  a.X = X;
+  a.T = T;
+  a.perm = perm;
+  a.batch = batch;
+  a.B = B;
+  a.in_p = s->in_p;
+  a.out_p = s->out_p;
+  a.nout = s->nout;
+  a.lw = (const float*)s->lw.p;
+  a.X0T = (__bf16*)s->X0T.p;
+  a.block_loss = (double*)s->bl.p;
+  return a;
+}
+
+FusedWeightsArgs fused_weights_args(hjg_surrogate* s, int B) {
+  FusedWeightsArgs a{};
+  a.L = s->L;
+  a.B = B;
+  int tiles = 0;
+  for (int l = 0; l < s->L; ++l) {
+    FusedLayer& Y = a.layer[l];
+    Y.A = l < s->depth ? (const __bf16*)s->dZTl[l].p : (const __bf16*)s->dYT.p;
+    Y.Bm = l == 0 ? (const __bf16*)s->X0T.p : (const __bf16*)s->XT[l - 1].p;
+    Y.fin = s->fin[l];
+    Y.fout = s->fout[l];
+    Y.woff = s->woff[l];
+    Y.boff = s->boff[l];
+    Y.Wb = (__bf16*)s->Wb[l].p;
+    Y.WbT = (__bf16*)s->WbT[l].p;
+    Y.tiles_n = s->fin[l] / 32;
+    Y.first = tiles;
+    tiles += (s->fout[l] / 32) * Y.tiles_n;
+  }
+  a.tiles = tiles;
+  a.w = (float*)s->w.p;
+  a.g = (float*)s->g.p;
+  a.m = (float*)s->m.p;
+  a.v = (float*)s->v.p;
+  a.block_loss = (const double*)s->bl.p;
+  a.nbl = B / kFusedRows;
+  a.acc = (double*)s->acc.p;
+  return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -309,6 +386,8 @@ int hjg_surrogate_create(hjg_ctx* ctx, int32_t n, int32_t width, int32_t depth, 
     if ((rc = grow(s->WbT[l], (size_t)s->fin[l] * s->fout[l] * 2))) return cleanup(rc);
   }
   if ((rc = grow(s->norm, 4 * s->nin * 4))) return cleanup(rc);
+  if ((rc = grow(s->ticket, 256))) return cleanup(rc);
+  if (hipMemset(s->ticket.p, 0, 256) != hipSuccess) return cleanup(fail(HJG_EHIP, "ticket initialisation failed"));
   if ((rc = grow(s->lw, s->out_p * 4))) return cleanup(rc);
   // Uniform initial weights, He scale sqrt(6/fan_in) for the SiLU layers and
   // Glorot scale sqrt(6/(fan_in+fan_out)) for the linear output layer (zero
@@ -510,8 +589,16 @@ int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x, const f
                             st));
   SG_HIP(launch_prep_targets(v, grad, s->n, B, s->out_p, nrm(s, 2), nrm(s, 3), (float*)s->T.p, st));
   SG_HIP(hipMemsetAsync(s->acc.p, 0, 8, st));
-  if ((rc = forward(s, B, true, st))) return rc;
-  if ((rc = backward(s, B, st))) return rc;
+  if (fused_ok(s, B)) {
+    const FusedRowsArgs ra = fused_rows_args(s, (int)B, (const __bf16*)s->X0.p, (const float*)s->T.p, nullptr, nullptr);
+    SG_HIP(launch_fused_rows(ra, s->width, s->depth, st));
+    FusedWeightsArgs wa = fused_weights_args(s, (int)B);
+    wa.adam = 0;
+    SG_HIP(launch_fused_weights(wa, st));
+  } else {
+    if ((rc = forward(s, B, true, st))) return rc;
+    if ((rc = backward(s, B, st))) return rc;
+  }
   double l = 0.0;
   SG_HIP(hipMemcpyAsync(&l, s->acc.p, 8, hipMemcpyDeviceToHost, st));
   SG_HIP(hipStreamSynchronize(st));
@@ -574,8 +661,30 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
     tab.Wb[l] = (__bf16*)s->Wb[l].p;
     tab.WbT[l] = (__bf16*)s->WbT[l].p;
   }
+  const bool fused = fused_ok(s, B);
+  FusedRowsArgs fra{};
+  FusedWeightsArgs fwa{};
+  if (fused) {
+    fra = fused_rows_args(s, B, (const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, ctr + 2);
+    fwa = fused_weights_args(s, B);
+    fwa.adam = 1;
+    fwa.ctr = ctr;
+    fwa.ticket = (int*)s->ticket.p;
+    fwa.lr_max = cfg->lr;
+    fwa.lr_min = cfg->lr_min;
+    fwa.total = total;
+    fwa.b1 = (float)cfg->beta1;
+    fwa.b2 = (float)cfg->beta2;
+    fwa.eps = (float)cfg->eps;
+    fwa.wd = (float)cfg->weight_decay;
+  }
   auto train_step = [&](hipStream_t q) -> int {
     int r;
+    if (fused) {
+      SG_HIP(launch_fused_rows(fra, s->width, s->depth, q));
+      SG_HIP(launch_fused_weights(fwa, q));
+      return HJG_OK;
+    }
     SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, B, s->in_p,
                          s->out_p, ctr + 2, (__bf16*)s->X0.p, (__bf16*)s->X0T.p, (float*)s->T.p, q));
     if ((r = forward(s, B, true, q))) return r;
