@@ -20,28 +20,28 @@ constexpr int R = kFusedRows;
 // logistic function with the hardware reciprocal (as every network kernel)
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
-// Shapes of one product of the rows kernel: out[16][N] = src[16][K] W^T.
-// The wave owns the 16-column tiles wave, wave + 4, ... (NT < 4: waves
-// beyond NT repeat tile wave % NT and store nothing).
-template <int K, int N>
+// Shapes of one product of the rows kernel: out[16][N] = src[16][K] W^T over
+// NW waves.  The wave owns the 16-column tiles wave, wave + NW, ... (NT < NW:
+// waves beyond NT repeat tile wave % NT and store nothing).
+template <int K, int N, int NW>
 struct PhaseShape {
-  static constexpr int NT = N / 16, TW = NT >= 4 ? NT / 4 : 1, KSP = K / 32;
-  static_assert(N % 16 == 0 && K % 32 == 0 && (NT < 4 || NT % 4 == 0), "phase shape");
+  static constexpr int NT = N / 16, TW = NT >= NW ? NT / NW : 1, KSP = K / 32;
+  static_assert(N % 16 == 0 && K % 32 == 0 && (NT < NW || NT % NW == 0), "phase shape");
 };
 
-template <int K, int N>
-using PhaseW = bf16x8[PhaseShape<K, N>::TW][PhaseShape<K, N>::KSP];
+template <int K, int N, int NW>
+using PhaseW = bf16x8[PhaseShape<K, N, NW>::TW][PhaseShape<K, N, NW>::KSP];
 
 // Operand lanes of v_mfma_f32_16x16x32_bf16: A[i = l%16][k = 8(l/16)..+7],
 // B[k = 8(l/16)..+7][j = l%16]; result lane l holds rows 4(l/16)..+3 of
 // column l%16.  Every load and product of a phase is unconditional, so the
 // weights of the next phase stay in flight while this phase computes.
-template <int K, int N>
-__device__ __forceinline__ void load_phase(const __bf16* W, int wave, int lane, PhaseW<K, N>& w) {
-  using S = PhaseShape<K, N>;
+template <int K, int N, int NW>
+__device__ __forceinline__ void load_phase(const __bf16* W, int wave, int lane, PhaseW<K, N, NW>& w) {
+  using S = PhaseShape<K, N, NW>;
 #pragma unroll
   for (int j = 0; j < S::TW; ++j) {
-    const int t = S::NT >= 4 ? wave + 4 * j : wave % S::NT;
+    const int t = S::NT >= NW ? wave + NW * j : wave % S::NT;
     const __bf16* row = W + (int64_t)(16 * t + (lane & 15)) * K + 8 * (lane >> 4);
 #pragma unroll
     for (int ks = 0; ks < S::KSP; ++ks) w[j][ks] = *reinterpret_cast<const bf16x8*>(row + 32 * ks);
@@ -51,48 +51,50 @@ __device__ __forceinline__ void load_phase(const __bf16* W, int wave, int lane, 
 }  // namespace
 
 // Rows kernel for a network of hidden width W, padded input IN, padded output
-// OUT and D hidden layers: phases 0..D forward (D hidden, then the output with
-// the loss), then D backward products (errors of hidden layers D-1 .. 0).
-template <int W, int IN, int OUT, int D>
-__global__ __launch_bounds__(256) void fused_rows_kernel(FusedRowsArgs a) {
+// OUT and D hidden layers, NW waves per block: phases 0..D forward (D hidden,
+// then the output with the loss), then D backward products (errors of hidden
+// layers D-1 .. 0).
+template <int W, int IN, int OUT, int D, int NW>
+__global__ __launch_bounds__(64 * NW) void fused_rows_kernel(FusedRowsArgs a) {
+  constexpr int NTH = 64 * NW;
   constexpr int WX = W > IN ? (W > OUT ? W : OUT) : (IN > OUT ? IN : OUT);
   constexpr int LH = WX + 8;
   __shared__ __attribute__((aligned(16))) __bf16 hbuf[2][R][LH];
   __shared__ float zs[D][R][W];
   __shared__ float bias[D + 1][WX];
-  __shared__ float tgt[R][OUT];
+  __shared__ __attribute__((aligned(16))) float tgt[R][OUT];
   __shared__ float lws[OUT];
-  __shared__ int srow[R];
-  __shared__ double red[4];
+  __shared__ double red[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = blockIdx.x * R;
-  const int64_t bidx = a.batch ? *a.batch : 0;
-  if (tid < R) srow[tid] = a.perm ? a.perm[bidx * a.B + r0 + tid] : r0 + tid;
 #pragma unroll
   for (int l = 0; l <= D; ++l) {
     const int nl = l < D ? W : OUT;
-    for (int c = tid; c < nl; c += 256) bias[l][c] = a.ph[l].bias[c];
+    for (int c = tid; c < nl; c += NTH) bias[l][c] = a.ph[l].bias[c];
   }
-  for (int c = tid; c < OUT; c += 256) lws[c] = c < a.nout ? a.lw[c] : 0.f;
+  for (int c = tid; c < OUT; c += NTH) lws[c] = c < a.nout ? a.lw[c] : 0.f;
   __syncthreads();
-  for (int e = tid; e < R * (IN / 8); e += 256) {
+  const __bf16* xb = a.X + (a.row0 + r0) * IN;
+  const float* tb = a.T + (a.row0 + r0) * OUT;
+  for (int e = tid; e < R * (IN / 8); e += NTH) {
     const int r = e / (IN / 8), c = (e % (IN / 8)) * 8;
-    *reinterpret_cast<bf16x8*>(&hbuf[0][r][c]) = *reinterpret_cast<const bf16x8*>(a.X + (int64_t)srow[r] * IN + c);
+    *reinterpret_cast<bf16x8*>(&hbuf[0][r][c]) = *reinterpret_cast<const bf16x8*>(xb + r * IN + c);
   }
-  for (int e = tid; e < R * OUT; e += 256) {
-    const int r = e / OUT, c = e % OUT;
-    tgt[r][c] = a.T[(int64_t)srow[r] * OUT + c];
+  for (int e = tid; e < R * (OUT / 4); e += NTH) {
+    const int r = e / (OUT / 4), c = (e % (OUT / 4)) * 4;
+    *reinterpret_cast<f32x4*>(&tgt[r][c]) = *reinterpret_cast<const f32x4*>(tb + r * OUT + c);
   }
   __syncthreads();
-  for (int c = tid; c < IN; c += 256) {
+  for (int c = tid; c < IN; c += NTH) {
     bf16x8 lo, hi;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       lo[r] = hbuf[0][r][c];
       hi[r] = hbuf[0][8 + r][c];
     }
-    *reinterpret_cast<bf16x8*>(a.X0T + (int64_t)c * a.B + r0) = lo;
-    *reinterpret_cast<bf16x8*>(a.X0T + (int64_t)c * a.B + r0 + 8) = hi;
+    __bf16* dst = a.X0T + (int64_t)(r0 >> 6) * (IN * 64) + c * 64 + (r0 & 63);
+    *reinterpret_cast<bf16x8*>(dst) = lo;
+    *reinterpret_cast<bf16x8*>(dst + 8) = hi;
   }
 
   double loss = 0.0;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void fused_rows_kernel(FusedRowsArgs a) {
     constexpr int N = FWD ? (L == D ? OUT : W) : W;
     constexpr int KIND = FWD ? (L < D ? PH_FWD_HIDDEN : PH_FWD_OUT) : PH_BWD;
     constexpr int S = PHI % 2;
-    using SH = PhaseShape<K, N>;
+    using SH = PhaseShape<K, N, NW>;
     const FusedPhase& P = a.ph[PHI];
     f32x4 acc[SH::TW];
 #pragma unroll
@@ -117,10 +119,10 @@ __global__ __launch_bounds__(256) void fused_rows_kernel(FusedRowsArgs a) {
 #pragma unroll
       for (int j = 0; j < SH::TW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w[j][ks], acc[j], 0, 0, 0);
     }
-    const bool owner = SH::NT >= 4 || wave < SH::NT;
+    const bool owner = SH::NT >= NW || wave < SH::NT;
 #pragma unroll
     for (int j = 0; j < SH::TW; ++j) {
-      const int t = SH::NT >= 4 ? wave + 4 * j : wave % SH::NT;
+      const int t = SH::NT >= NW ? wave + NW * j : wave % SH::NT;
       const int col = 16 * t + (lane & 15);
       bf16x4 o;
 #pragma unroll
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void fused_rows_kernel(FusedRowsArgs a) {
         if (owner) hbuf[1 - S][row][col] = hv;
         o[v] = hv;
       }
-      if (owner) *reinterpret_cast<bf16x4*>(P.outT + (int64_t)col * a.B + r0 + rb) = o;
+      if (owner) *reinterpret_cast<bf16x4*>(P.outT + (int64_t)(r0 >> 6) * (N * 64) + col * 64 + (r0 & 63) + rb) = o;
     }
     __syncthreads();
   };
@@ -159,150 +161,174 @@ __global__ __launch_bounds__(256) void fused_rows_kernel(FusedRowsArgs a) {
       constexpr int LN = FN ? PN : 2 * D + 1 - PN;
       constexpr int KN = FN ? (LN == 0 ? IN : W) : (LN == D ? OUT : W);
       constexpr int NN = FN ? (LN == D ? OUT : W) : W;
-      PhaseW<KN, NN> wn;
-      load_phase<KN, NN>(a.ph[PN].W, wave, lane, wn);
+      PhaseW<KN, NN, NW> wn;
+      load_phase<KN, NN, NW>(a.ph[PN].W, wave, lane, wn);
       run(ph, wcur);
       self(std::integral_constant<int, PN>{}, wn, self);
     } else {
       run(ph, wcur);
     }
   };
-  PhaseW<IN, W> w0;
-  load_phase<IN, W>(a.ph[0].W, wave, lane, w0);
+  PhaseW<IN, W, NW> w0;
+  load_phase<IN, W, NW>(a.ph[0].W, wave, lane, w0);
   step(std::integral_constant<int, 0>{}, w0, step);
   // ---- the block's loss (fixed order)
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_down(loss, off, 64);
   if (lane == 0) red[wave] = loss;
   __syncthreads();
-  if (tid == 0) a.block_loss[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) {
+    double sl = 0.0;
+    for (int w = 0; w < NW; ++w) sl += red[w];
+    a.block_loss[blockIdx.x] = sl;
+  }
 }
 
 // One 32 x 32 tile of one layer's weight gradient: dW[m][n] = sum_b dz^T[m][b] h^T[n][b].
 // Operand lanes of v_mfma_f32_32x32x16_bf16: A[i = l%32][k = 8(l/32)..+7],
 // B[k = 8(l/32)..+7][j = l%32]; result lane l holds rows 8(v/4) + 4(l/32) + v%4
-// of column l%32.  The four waves take a quarter of the batch each; the
-// operands of 16 k-steps are requested before their products (and the next
-// 16 before those products run).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void fused_weights_kernel(
-    FusedWeightsArgs a) {
-  __shared__ float part[4][16][64];
-  __shared__ float rpart[4][64];
+// of column l%32.  The NWV waves split the batch (NST k-steps of 16 each); the
+// loop is unrolled at compile time, the operands of the next 16 k-steps
+// requested before the products of the current 16.
+// Consecutive blocks go to different XCDs (round robin), so tiles are
+// assigned in contiguous ranges per XCD: the tiles of one range share their
+// row blocks of dz^T in that XCD's L2.
+template <int NST, int NWV>
+__global__ __launch_bounds__(64 * NWV) void fused_weights_kernel(FusedWeightsArgs a) {
+  constexpr int CH = NST < 16 ? NST : 16;   // k-steps per chunk
+  constexpr int NCH = NST / CH;
+  static_assert(NST % CH == 0, "k-steps per wave");
+  __shared__ float part[NWV][16][64];
+  __shared__ float rpart[NWV][64];
   __shared__ float sched[3];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int b = blockIdx.x;
+  const int nx = 8, q8 = a.tiles / nx, r8 = a.tiles % nx, x = blockIdx.x % nx;
+  const int b = x * q8 + (x < r8 ? x : r8) + (int)blockIdx.x / nx;
   int l = 0;
   while (l + 1 < a.L && b >= a.layer[l + 1].first) ++l;
   const FusedLayer& Y = a.layer[l];
   const int t = b - Y.first;
   const int m0 = 32 * (t / Y.tiles_n), n0 = 32 * (t % Y.tiles_n);
-  const bool rowsum = n0 == 0;
-  const int kw = a.B / 4, kb = wave * kw;
-  const __bf16* arow = Y.A + (int64_t)(m0 + (lane & 31)) * a.B + kb + 8 * (lane >> 5);
-  const __bf16* brow = Y.Bm + (int64_t)(n0 + (lane & 31)) * a.B + kb + 8 * (lane >> 5);
+  const int kb = wave * (16 * NST);
+  const int h8 = 8 * (lane >> 5);
+  const __bf16* abase = Y.A + (m0 + (lane & 31)) * 64;
+  const __bf16* bbase = Y.Bm + (n0 + (lane & 31)) * 64;
+  const int64_t fa = (int64_t)Y.fout * 64, fb = (int64_t)Y.fin * 64;
+  // operands of k-step st: batch columns kb + 16 st + h8 .. + 7 (one 64-column block)
+  auto aptr = [&](int st) {
+    const int k = kb + 16 * st + h8;
+    return reinterpret_cast<const bf16x8*>(abase + (k >> 6) * fa + (k & 63));
+  };
+  auto bptr = [&](int st) {
+    const int k = kb + 16 * st + h8;
+    return reinterpret_cast<const bf16x8*>(bbase + (k >> 6) * fb + (k & 63));
+  };
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
   float rs = 0.f;
-  constexpr int CH = 16;   // k-steps per chunk
-  const int nst = kw / 16;
   bf16x8 av[2][CH], bv[2][CH];
-  auto load = [&](int c, int buf) {
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int st = c * CH + i;
-      if (st < nst) {
-        av[buf][i] = *reinterpret_cast<const bf16x8*>(arow + 16 * st);
-        bv[buf][i] = *reinterpret_cast<const bf16x8*>(brow + 16 * st);
+  for (int i = 0; i < CH; ++i) {
+    av[0][i] = *aptr(i);
+    bv[0][i] = *bptr(i);
+  }
+  // the epilogue's operands, requested now so that they arrive during the
+  // products: this step's schedule, the thread's parameters and moments
+  // (column n0 + tid % 32, rows m0 + 4 (tid / 32) .. + 3), the bias entries,
+  // the rows kernel's loss sums
+  const float sch = a.adam && tid < 3 ? a.sched[tid] : 0.f;
+  const int n = n0 + (tid & 31), mr = m0 + 4 * (tid >> 5);
+  const bool bias_row = n0 == 0 && tid < 32;
+  float wq[4], mq[4], vq[4], wbias = 0.f, mbias = 0.f, vbias = 0.f;
+  if (a.adam && tid < 256) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t idx = Y.woff + (int64_t)(mr + q) * Y.fin + n;
+      wq[q] = a.w[idx];
+      mq[q] = a.m[idx];
+      vq[q] = a.v[idx];
+    }
+  }
+  if (a.adam && bias_row) {
+    wbias = a.w[Y.boff + m0 + tid];
+    mbias = a.m[Y.boff + m0 + tid];
+    vbias = a.v[Y.boff + m0 + tid];
+  }
+  const bool loss_wave = blockIdx.x == 0 && wave == 0 && a.acc;
+  double blv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (loss_wave) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (lane + 64 * j < a.nbl) blv[j] = a.block_loss[lane + 64 * j];
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        av[1 - cur][i] = *aptr((c + 1) * CH + i);
+        bv[1 - cur][i] = *bptr((c + 1) * CH + i);
       }
     }
-  };
-  auto compute = [&](int c, int buf) {
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
-      if (c * CH + i < nst) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[buf][i], bv[buf][i], acc, 0, 0, 0);
-        if (rowsum) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][i], bv[cur][i], acc, 0, 0, 0);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) rs += (float)av[buf][i][e];
-        }
-      }
-    }
-  };
-  const int nch = (nst + CH - 1) / CH;
-  load(0, 0);
-  for (int c = 0; c < nch; c += 2) {
-    if (c + 1 < nch) load(c + 1, 1);
-    compute(c, 0);
-    if (c + 1 < nch) {
-      if (c + 2 < nch) load(c + 2, 0);
-      compute(c + 1, 1);
+      for (int e = 0; e < 8; ++e) rs += (float)av[cur][i][e];
     }
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v) part[wave][v][lane] = acc[v];
-  if (rowsum) rpart[wave][lane] = rs;
-  if (tid == 0 && a.adam) {
-    const double k = (double)a.ctr[0], step = (double)(a.ctr[1] + 1);
-    sched[0] = (float)(a.lr_min + 0.5 * (a.lr_max - a.lr_min) * (1.0 + cos(M_PI * k / (double)a.total)));
-    sched[1] = (float)(1.0 - pow((double)a.b1, step));
-    sched[2] = (float)(1.0 - pow((double)a.b2, step));
-  }
+  rpart[wave][lane] = rs;
+  if (tid < 3) sched[tid] = sch;
   __syncthreads();
   const float lr = a.adam ? sched[0] : 0.f, bc1 = a.adam ? sched[1] : 1.f, bc2 = a.adam ? sched[2] : 1.f;
-  auto update = [&](int64_t idx, float gi) -> float {
-    const float mi = a.b1 * a.m[idx] + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * a.v[idx] + (1.0f - a.b2) * gi * gi;
+  auto update = [&](int64_t idx, float gi, float wo, float mo, float vo) -> float {
+    const float mi = a.b1 * mo + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * vo + (1.0f - a.b2) * gi * gi;
     a.m[idx] = mi;
     a.v[idx] = vi;
     const float mh = mi / bc1, vh = vi / bc2;
-    const float wi = a.w[idx] - lr * (mh / (sqrtf(vh) + a.eps) + a.wd * a.w[idx]);
+    const float wi = wo - lr * (mh / (sqrtf(vh) + a.eps) + a.wd * wo);
     a.w[idx] = wi;
     return wi;
   };
-  // the tile's 1,024 sums, four per thread, the waves added in order
+  // the thread's entries are 4 (tid / 64) + q of lane tid % 64 in every
+  // wave's result
+  bf16x4 wt;
+  if (tid < 256) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = 4 * tid + q;
-    const int v = e / 64, ln = e % 64;
-    const float gsum = ((part[0][v][ln] + part[1][v][ln]) + part[2][v][ln]) + part[3][v][ln];
-    const int m = m0 + 8 * (v / 4) + 4 * (ln >> 5) + (v % 4), n = n0 + (ln & 31);
-    const int64_t idx = Y.woff + (int64_t)m * Y.fin + n;
-    if (a.adam) {
-      const __bf16 wb = (__bf16)update(idx, gsum);
-      Y.Wb[(int64_t)m * Y.fin + n] = wb;
-      Y.WbT[(int64_t)n * Y.fout + m] = wb;
-    } else {
-      a.g[idx] = gsum;
-    }
-  }
-  if (rowsum && tid < 32) {
-    float gsum = 0.f;
+    for (int q = 0; q < 4; ++q) {
+      const int v = 4 * (tid >> 6) + q;
+      float gsum = part[0][v][lane];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) gsum += rpart[w][tid] + rpart[w][tid + 32];
-    const int64_t idx = Y.boff + m0 + tid;
-    if (a.adam) (void)update(idx, gsum);
-    else a.g[idx] = gsum;
-  }
-  if (b == 0 && tid == 0 && a.acc) {
-    double s = 0.0;
-    for (int i = 0; i < a.nbl; ++i) s += a.block_loss[i];
-    a.acc[0] += s;
-  }
-  // the last block to finish advances the step counters for the next step
-  if (a.ticket) {
-    __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const int done = atomicAdd(a.ticket, 1);
-      if (done == (int)gridDim.x - 1) {
-        int64_t* ctr = const_cast<int64_t*>(a.ctr);
-        ctr[0] += 1;
-        ctr[1] += 1;
-        ctr[2] += 1;
-        *a.ticket = 0;
-        __threadfence();
+      for (int w = 1; w < NWV; ++w) gsum += part[w][v][lane];
+      const int64_t idx = Y.woff + (int64_t)(mr + q) * Y.fin + n;
+      if (a.adam) {
+        const __bf16 wb = (__bf16)update(idx, gsum, wq[q], mq[q], vq[q]);
+        Y.Wb[(int64_t)(mr + q) * Y.fin + n] = wb;
+        wt[q] = wb;
+      } else {
+        a.g[idx] = gsum;
       }
     }
+    if (a.adam) *reinterpret_cast<bf16x4*>(Y.WbT + (int64_t)n * Y.fout + mr) = wt;
+  }
+  if (bias_row) {
+    float gsum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w) gsum += rpart[w][tid] + rpart[w][tid + 32];
+    const int64_t idx = Y.boff + m0 + tid;
+    if (a.adam) (void)update(idx, gsum, wbias, mbias, vbias);
+    else a.g[idx] = gsum;
+  }
+  // the step's loss: the rows kernel's block sums added in a fixed order
+  if (loss_wave) {
+    const double sl0 = (blv[0] + blv[1]) + (blv[2] + blv[3]);
+    double sl = sl0;
+    for (int off = 32; off > 0; off >>= 1) sl += __shfl_down(sl, off, 64);
+    if (lane == 0) a.acc[0] += sl;
   }
 }
 
@@ -310,7 +336,8 @@ namespace {
 
 template <int W, int P, int D>
 hipError_t rows_launch(const FusedRowsArgs& a, hipStream_t s) {
-  fused_rows_kernel<W, P, P, D><<<a.B / R, 256, 0, s>>>(a);
+  constexpr int NW = W >= 128 ? 8 : 4;
+  fused_rows_kernel<W, P, P, D, NW><<<a.B / R, 64 * NW, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -350,8 +377,50 @@ hipError_t launch_fused_rows(const FusedRowsArgs& a, int width, int depth, hipSt
   return hipErrorInvalidValue;
 }
 
+namespace {
+
+__global__ void permute_rows_kernel(const __bf16* X, const float* T, const int* perm, int64_t M, int in_p,
+                                    int out_p, __bf16* Xp, float* Tp) {
+  const int cx = in_p / 8, ct = out_p / 4;   // 16-byte pieces per row
+  const int64_t total = M * (cx + ct);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / (cx + ct);
+    const int c = (int)(e % (cx + ct));
+    const int64_t src = perm[i];
+    if (c < cx)
+      *reinterpret_cast<bf16x8*>(Xp + i * in_p + 8 * c) = *reinterpret_cast<const bf16x8*>(X + src * in_p + 8 * c);
+    else
+      *reinterpret_cast<f32x4*>(Tp + i * out_p + 4 * (c - cx)) =
+          *reinterpret_cast<const f32x4*>(T + src * out_p + 4 * (c - cx));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_permute_rows(const __bf16* X, const float* T, const int* perm, int64_t M, int in_p, int out_p,
+                               __bf16* Xp, float* Tp, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (in_p % 8 || out_p % 4) return hipErrorInvalidValue;
+  const int64_t total = M * (in_p / 8 + out_p / 4);
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  permute_rows_kernel<<<grid, 256, 0, s>>>(X, T, perm, M, in_p, out_p, Xp, Tp);
+  return hipGetLastError();
+}
+
+bool fused_weights_supported(int B) { return B == 256 || B == 512 || B == 1024 || B == 2048 || B == 4096; }
+
 hipError_t launch_fused_weights(const FusedWeightsArgs& a, hipStream_t s) {
-  fused_weights_kernel<<<a.tiles, 256, 0, s>>>(a);
+  constexpr int NWV = 8;
+  if (a.nbl > 256) return hipErrorInvalidValue;   // the loss wave reads at most four sums per lane
+  const dim3 g(a.tiles), blk(64 * NWV);
+  switch (a.B) {
+    case 256: fused_weights_kernel<2, NWV><<<g, blk, 0, s>>>(a); break;
+    case 512: fused_weights_kernel<4, NWV><<<g, blk, 0, s>>>(a); break;
+    case 1024: fused_weights_kernel<8, NWV><<<g, blk, 0, s>>>(a); break;
+    case 2048: fused_weights_kernel<16, NWV><<<g, blk, 0, s>>>(a); break;
+    case 4096: fused_weights_kernel<32, NWV><<<g, blk, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct hjg_surrogate {
   std::vector<Buf> Z, X, XT;
   Buf dZ[2], dZT[2];
   std::vector<Buf> dZTl;            // fused step: transposed errors of each hidden layer [width][B]
-  Buf ticket;                       // fused step: blocks finished (zero between steps)
+  Buf Xp, Tp, sched;                // fused step: the epoch's permuted training set; per-step schedule
   // training set and sweep workspace
   Buf Xall, Tall, sv, sg, tq, flags, bcount, total, index, xfb, vfb, gfb;
   // time-marching step workspace
@@ -268,17 +268,17 @@ int backward(hjg_surrogate* s, int64_t rows, hipStream_t st) {
 }
 
 // The fused training step (two launches: rows, then weight gradients with
-// AdamW) serves the network shapes its rows kernel is instantiated for, on
-// batches that are a multiple of 64 rows; HJG_MLP_FUSED=0 selects the
-// layer-by-layer launches instead.
+// AdamW) serves the network shapes and batch sizes its kernels are
+// instantiated for; HJG_MLP_FUSED=0 selects the layer-by-layer launches
+// instead.
 bool fused_ok(const hjg_surrogate* s, int64_t B) {
   const char* e = std::getenv("HJG_MLP_FUSED");
   if (e && e[0] == '0') return false;
-  return fused_rows_supported(s->width, s->in_p, s->out_p, s->depth) && B % 64 == 0;
+  return fused_rows_supported(s->width, s->in_p, s->out_p, s->depth) && B <= INT32_MAX &&
+         fused_weights_supported((int)B);
 }
 
-FusedRowsArgs fused_rows_args(hjg_surrogate* s, int B, const __bf16* X, const float* T, const int* perm,
-                              const int64_t* batch) {
+FusedRowsArgs fused_rows_args(hjg_surrogate* s, int B, const __bf16* X, const float* T, int64_t row0) {
   FusedRowsArgs a{};
   const float* w = (const float*)s->w.p;
   int k = 0;
@@ -296,8 +296,7 @@ FusedRowsArgs fused_rows_args(hjg_surrogate* s, int B, const __bf16* X, const fl
   }
   a.X = X;
   a.T = T;
-  a.perm = perm;
-  a.batch = batch;
+  a.row0 = row0;
   a.B = B;
   a.in_p = s->in_p;
   a.out_p = s->out_p;
@@ -386,8 +385,6 @@ int hjg_surrogate_create(hjg_ctx* ctx, int32_t n, int32_t width, int32_t depth, 
     if ((rc = grow(s->WbT[l], (size_t)s->fin[l] * s->fout[l] * 2))) return cleanup(rc);
   }
   if ((rc = grow(s->norm, 4 * s->nin * 4))) return cleanup(rc);
-  if ((rc = grow(s->ticket, 256))) return cleanup(rc);
-  if (hipMemset(s->ticket.p, 0, 256) != hipSuccess) return cleanup(fail(HJG_EHIP, "ticket initialisation failed"));
   if ((rc = grow(s->lw, s->out_p * 4))) return cleanup(rc);
   // Uniform initial weights, He scale sqrt(6/fan_in) for the SiLU layers and
   // Glorot scale sqrt(6/(fan_in+fan_out)) for the linear output layer (zero
@@ -420,12 +417,15 @@ void hjg_surrogate_destroy(hjg_surrogate* s) {
                            &s->dYT, &s->part, &s->bl, &s->acc, &s->perm, &s->ctr, &s->Xall, &s->Tall, &s->sv,
                            &s->sg,
                            &s->tq, &s->flags, &s->bcount, &s->total, &s->index, &s->xfb, &s->vfb, &s->gfb,
-                           &s->dZ[0], &s->dZ[1], &s->dZT[0], &s->dZT[1]};
+                           &s->dZ[0], &s->dZ[1], &s->dZT[0], &s->dZT[1], &s->Xp, &s->Tp, &s->sched,
+                           &s->mt_table, &s->mt_zbar, &s->mt_c, &s->mt_th, &s->mt_vprev, &s->mt_pm, &s->mt_pS,
+                           &s->mt_pS2, &s->mt_pG, &s->mt_block, &s->mt_resid, &s->mt_ctrl};
   for (auto& b : s->Wb) all.push_back(&b);
   for (auto& b : s->WbT) all.push_back(&b);
   for (auto& b : s->Z) all.push_back(&b);
   for (auto& b : s->X) all.push_back(&b);
   for (auto& b : s->XT) all.push_back(&b);
+  for (auto& b : s->dZTl) all.push_back(&b);
   for (Buf* b : all)
     if (b->p) (void)hipFree(b->p);
   delete s;
@@ -590,7 +590,7 @@ int hjg_surrogate_loss_grad(hjg_surrogate* s, int64_t B, const float* x, const f
   SG_HIP(launch_prep_targets(v, grad, s->n, B, s->out_p, nrm(s, 2), nrm(s, 3), (float*)s->T.p, st));
   SG_HIP(hipMemsetAsync(s->acc.p, 0, 8, st));
   if (fused_ok(s, B)) {
-    const FusedRowsArgs ra = fused_rows_args(s, (int)B, (const __bf16*)s->X0.p, (const float*)s->T.p, nullptr, nullptr);
+    const FusedRowsArgs ra = fused_rows_args(s, (int)B, (const __bf16*)s->X0.p, (const float*)s->T.p, 0);
     SG_HIP(launch_fused_rows(ra, s->width, s->depth, st));
     FusedWeightsArgs wa = fused_weights_args(s, (int)B);
     wa.adam = 0;
@@ -647,10 +647,10 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
   const int64_t total = steps_per_epoch * cfg->epochs;
   if ((rc = grow(s->ctr, 3 * sizeof(int64_t)))) return rc;
   int64_t* ctr = (int64_t*)s->ctr.p;
-  // One training step: batch gather, forward, backward, AdamW (learning rate
-  // and bias corrections from the device counters) with the bf16 weight
-  // refresh, counter advance.  The first step runs directly (it also sizes
-  // every workspace); the rest replay it as a recorded graph.
+  // One training step: batch gather, forward, backward, AdamW with the bf16
+  // weight refresh.  The layer-by-layer step takes its batch, learning rate
+  // and bias corrections from device counters that it advances; its first
+  // step runs directly, the rest replay recorded graphs of one or G steps.
   if (s->L > kMaxLayers) return fail(HJG_EINVAL, "too many layers for the fused optimizer step");
   LayerTab tab{};
   tab.L = s->L;
@@ -662,29 +662,41 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
     tab.WbT[l] = (__bf16*)s->WbT[l].p;
   }
   const bool fused = fused_ok(s, B);
+  const char* ng = std::getenv("HJG_NO_GRAPH");       // 1: every step launched directly (for comparison)
+  const bool use_graph = !(ng && ng[0] == '1');
+  // The fused step takes fixed arguments: its rows of the epoch's permuted
+  // training set and its entry of the epoch's schedule table (learning rate
+  // and bias corrections formed on the host), so a whole epoch records as
+  // one graph (up to kEpochGraphSteps steps; longer epochs launch directly).
+  constexpr int64_t kEpochGraphSteps = 8192;
   FusedRowsArgs fra{};
   FusedWeightsArgs fwa{};
+  std::vector<float> hsched;
   if (fused) {
-    fra = fused_rows_args(s, B, (const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, ctr + 2);
+    if ((rc = grow(s->Xp, (size_t)steps_per_epoch * B * s->in_p * 2)) ||
+        (rc = grow(s->Tp, (size_t)steps_per_epoch * B * s->out_p * 4)) ||
+        (rc = grow(s->sched, (size_t)steps_per_epoch * 3 * 4)))
+      return rc;
+    fra = fused_rows_args(s, B, (const __bf16*)s->Xp.p, (const float*)s->Tp.p, 0);
     fwa = fused_weights_args(s, B);
     fwa.adam = 1;
-    fwa.ctr = ctr;
-    fwa.ticket = (int*)s->ticket.p;
-    fwa.lr_max = cfg->lr;
-    fwa.lr_min = cfg->lr_min;
-    fwa.total = total;
     fwa.b1 = (float)cfg->beta1;
     fwa.b2 = (float)cfg->beta2;
     fwa.eps = (float)cfg->eps;
     fwa.wd = (float)cfg->weight_decay;
+    hsched.resize((size_t)steps_per_epoch * 3);
   }
+  auto fused_step = [&](int64_t b, hipStream_t q) -> int {
+    FusedRowsArgs ra = fra;
+    ra.row0 = b * B;
+    FusedWeightsArgs wa = fwa;
+    wa.sched = (const float*)s->sched.p + 3 * b;
+    SG_HIP(launch_fused_rows(ra, s->width, s->depth, q));
+    SG_HIP(launch_fused_weights(wa, q));
+    return HJG_OK;
+  };
   auto train_step = [&](hipStream_t q) -> int {
     int r;
-    if (fused) {
-      SG_HIP(launch_fused_rows(fra, s->width, s->depth, q));
-      SG_HIP(launch_fused_weights(fwa, q));
-      return HJG_OK;
-    }
     SG_HIP(launch_gather((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p, B, s->in_p,
                          s->out_p, ctr + 2, (__bf16*)s->X0.p, (__bf16*)s->X0T.p, (float*)s->T.p, q));
     if ((r = forward(s, B, true, q))) return r;
@@ -695,17 +707,35 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
     SG_HIP(launch_advance_counters(ctr, q));
     return HJG_OK;
   };
+  // Recorded graphs: the fused path's epoch (index 2); the layer-by-layer
+  // path's one and G steps (indices 0, 1: the device counters move every step
+  // on, so a graph of G steps replays G consecutive steps).
+  const int64_t G = std::min<int64_t>(16, steps_per_epoch);
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   auto release = [&](int code) {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < 3; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
     if (cap) (void)hipStreamDestroy(cap);
     return code;
   };
-  const char* ng = std::getenv("HJG_NO_GRAPH");       // 1: every step launched directly (for comparison)
-  const bool use_graph = !(ng && ng[0] == '1');
+  auto record = [&](int i) -> int {
+    if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(HJG_EHIP, "training: graph capture could not start");
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(HJG_EHIP, "training: graph capture could not start");
+    int r = HJG_OK;
+    const int64_t steps = i == 2 ? steps_per_epoch : i == 1 ? G : 1;
+    for (int64_t k = 0; k < steps && !r; ++k) r = i == 2 ? fused_step(k, cap) : train_step(cap);
+    const hipError_t ec = hipStreamEndCapture(cap, &graph[i]);
+    if (r) return r;
+    if (ec != hipSuccess || hipGraphInstantiate(&exec[i], graph[i], nullptr, nullptr, 0) != hipSuccess)
+      return fail(HJG_EHIP, "training: graph capture failed");
+    return HJG_OK;
+  };
   std::vector<int> perm(M);
   uint64_t seed = cfg->seed;
   for (int e = 0; e < cfg->epochs; ++e) {
@@ -719,21 +749,36 @@ int hjg_surrogate_train(hjg_surrogate* s, int64_t M, const float* x, const float
         hipMemcpyAsync(ctr, c0, sizeof(c0), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemsetAsync(s->acc.p, 0, 8, st) != hipSuccess)
       return release(fail(HJG_EHIP, "training: upload of the epoch's order failed"));
-    for (int64_t b = 0; b < steps_per_epoch; ++b) {
-      if (use_graph && !exec && (e > 0 || b > 0)) {
-        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-          return release(fail(HJG_EHIP, "training: graph capture could not start"));
-        rc = train_step(cap);
-        const hipError_t ec = hipStreamEndCapture(cap, &graph);
-        if (rc) return release(rc);
-        if (ec != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
-          return release(fail(HJG_EHIP, "training: graph capture failed"));
+    if (fused) {
+      // cosine learning rate at global step k, bias corrections at optimizer step t
+      for (int64_t b = 0; b < steps_per_epoch; ++b) {
+        const double k = (double)(e * steps_per_epoch + b), t_opt = (double)(s->step + e * steps_per_epoch + b + 1);
+        hsched[3 * b] = (float)(cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * k / (double)total)));
+        hsched[3 * b + 1] = (float)(1.0 - std::pow((double)(float)cfg->beta1, t_opt));
+        hsched[3 * b + 2] = (float)(1.0 - std::pow((double)(float)cfg->beta2, t_opt));
       }
-      if (exec) {
-        if (hipGraphLaunch(exec, st) != hipSuccess) return release(fail(HJG_EHIP, "training: graph launch failed"));
-      } else if ((rc = train_step(st))) {
-        return release(rc);
+      if (hipMemcpyAsync(s->sched.p, hsched.data(), hsched.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+        return release(fail(HJG_EHIP, "training: upload of the epoch's schedule failed"));
+      SG_HIP(launch_permute_rows((const __bf16*)s->Xall.p, (const float*)s->Tall.p, (const int*)s->perm.p,
+                                 steps_per_epoch * B, s->in_p, s->out_p, (__bf16*)s->Xp.p, (float*)s->Tp.p, st));
+      if (use_graph && steps_per_epoch <= kEpochGraphSteps) {
+        if (!exec[2] && (rc = record(2))) return release(rc);
+        if (hipGraphLaunch(exec[2], st) != hipSuccess) return release(fail(HJG_EHIP, "training: graph launch failed"));
+      } else {
+        for (int64_t b = 0; b < steps_per_epoch; ++b)
+          if ((rc = fused_step(b, st))) return release(rc);
+      }
+    } else {
+      for (int64_t b = 0; b < steps_per_epoch;) {
+        if (!use_graph || (e == 0 && b == 0)) {
+          if ((rc = train_step(st))) return release(rc);
+          ++b;
+          continue;
+        }
+        const int i = steps_per_epoch - b >= G ? 1 : 0;
+        if (!exec[i] && (rc = record(i))) return release(rc);
+        if (hipGraphLaunch(exec[i], st) != hipSuccess) return release(fail(HJG_EHIP, "training: graph launch failed"));
+        b += i ? G : 1;
       }
     }
     double acc = 0.0;
