@@ -943,7 +943,23 @@ def main():
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only measure the issue rate of independent float32 FMAs at 1..8 waves per SIMD")
     args = ap.parse_args()
+    if args.valu_probe:
+        from paper_2605_18566_amd import probe_valu_rate
+        rows = []
+        forms = {0: "fma acc*s+s (scalar operand)", 1: "fmac acc+=a*b", 2: "mul acc*=a", 3: "fma acc*a+b",
+                 4: "fmac acc+=s*a (scalar operand)", 5: "add acc+=s (scalar operand)", 6: "min3 (acc, a, b)"}
+        for form, what in forms.items():
+            for wps in (1, 2, 4, 8):
+                r, ghz = probe_valu_rate(wps, form=form)
+                rows.append({"form": what, "waves_per_simd": wps, "instr_per_cu_clock": round(r, 4),
+                             "clock_ghz": round(ghz, 4)})
+                print(f"{what}, waves/SIMD {wps}: {r:.3f} wave-level VALU instructions per CU-clock at "
+                      f"{ghz:.3f} GHz", file=sys.stderr, flush=True)
+        print(json.dumps({"valu_probe": rows, "peak_instr_per_cu_clock": 2.0}))
+        return
     if args.copy_bytes:
         import torch
         a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")

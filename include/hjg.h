@@ -50,10 +50,12 @@
  *    comparison (the defaults are the tuned ones): HJG_NO_MFMA=1,
  *    HJG_TARGET_BLOCKS=n, HJG_NO_GRAPH=1, HJG_BATCH_SPLIT=n,
  *    HJG_BATCH_PERSISTENT=0|1, HJG_BATCH_CONCURRENT=0|1, HJG_TUBE_FUSED=0,
- *    HJG_TUBE_ROWS=n.  The graph, launch-mode and row-chunk switches give
- *    the same bits; the path and split switches (HJG_NO_MFMA,
- *    HJG_TARGET_BLOCKS, HJG_BATCH_SPLIT, HJG_TUBE_FUSED) change the float32
- *    summation order, so results move at rounding level.
+ *    HJG_TUBE_ROWS=n, HJG_MLP_FUSED=0 (the surrogate's layer-by-layer
+ *    training step instead of the fused one).  The graph, launch-mode and
+ *    row-chunk switches give the same bits; the path and split switches
+ *    (HJG_NO_MFMA, HJG_TARGET_BLOCKS, HJG_BATCH_SPLIT, HJG_TUBE_FUSED,
+ *    HJG_MLP_FUSED) change the float32 summation order, so results move at
+ *    rounding level.
  */
 #ifndef HJG_H
 #define HJG_H
@@ -366,6 +368,23 @@ int hjg_autotune_batched(hjg_ctx* ctx, int32_t P, const hjg_problem* problems,
                          void* hip_stream);
 int hjg_tuning_save(const hjg_ctx* ctx, const char* path);
 int hjg_tuning_load(hjg_ctx* ctx, const char* path);
+
+/*
+ * Measurement helper (not part of the method): the issue rate of independent
+ * full-rate (unpacked) float32 operations with waves_per_simd (1..8) blocks
+ * of 4 waves resident per compute unit, each lane running 12 independent
+ * chains for iters x 8 steps.  form 0: acc = acc * s + s with scalar s
+ * (three-operand FMA); 1: acc += a * b with per-lane a, b (accumulating FMA);
+ * 2: acc *= a; 3: acc = acc * a + b (three-operand FMA, per-lane operands);
+ * 4: acc += s * a; 5: acc += s; 6: acc = min(acc, a, b).  Writes the wave-level VALU instructions per compute-unit
+ * clock (the chip's float32 vector peak, 157.3 TFLOP/s, is 2.0 per clock)
+ * and the shader clock in GHz measured by the waves (shader-clock ticks
+ * against the 100 MHz real-time counter).  Allocates a small workspace,
+ * synchronises the stream.  Errors: HJG_EINVAL (arguments), HJG_ENOMEM,
+ * HJG_EHIP.
+ */
+int hjg_probe_valu_rate(int32_t waves_per_simd, int32_t iters, int32_t form,
+                        double* instr_per_cu_clock, double* clock_ghz, void* hip_stream);
 
 /*
  * ------------------------------------------------------------------------

@@ -111,6 +111,8 @@ SIGNATURES = [
                                        C.POINTER(C.c_double), C.c_void_p]),
     ("hjg_tuning_save", C.c_int, [C.c_void_p, C.c_char_p]),
     ("hjg_tuning_load", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("hjg_probe_valu_rate", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.c_void_p]),
     ("hjg_surrogate_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                        C.POINTER(C.c_void_p)]),
     ("hjg_surrogate_destroy", None, [C.c_void_p]),

@@ -199,6 +199,7 @@ __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qb
 
     const int cnt = min(kMS, i_end - i0);
     auto group = [&](int g0, auto masked) {
+      const const_f32_p zg = zc + (int64_t)(i0 + g0) * ZS;   // the group's first sample row
       // ---- tilt contraction for both tiles, then regroup by own query
       f32x16_t ta, tb;
 #pragma unroll
@@ -221,12 +222,28 @@ __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qb
         a[v] = x0;        // sample 8(v/4) + v%4
         a[16 + v] = x1;   // sample 8(v/4) + 4 + v%4
       }
-      // ---- datum and log-weights of the lane's 32 pairs
+      // ---- datum and log-weights of the lane's 32 pairs.  Sample u's offsets
+      // and squared radii are computed in the same scheduling region as the
+      // square root and log-weight of sample u - 1, so the dependent tail of
+      // one sample overlaps the independent arithmetic of the next.
       auto coords = [&](int u) {
         const int j = g0 + 8 * ((u & 15) / 4) + 4 * (u / 16) + (u & 3);
-        int64_t row = i0 + j;
-        if constexpr (decltype(masked)::value) row = j < cnt ? row : i_end - 1;
-        return zc + row * ZS;
+        if constexpr (decltype(masked)::value) {
+          const int64_t row = j < cnt ? i0 + j : i_end - 1;
+          return zc + row * ZS;
+        } else {
+          return zg + (8 * ((u & 15) / 4) + 4 * (u / 16) + (u & 3)) * ZS;
+        }
+      };
+      auto finish = [&](int u, float mn) {
+        const float ell = __builtin_amdgcn_sqrtf(mn) - A.dp.r;
+        const float av = fmaf(-cl, ell, a0 - a[u]);
+        if constexpr (decltype(masked)::value) {
+          const int j = g0 + 8 * ((u & 15) / 4) + 4 * (u / 16) + (u & 3);
+          a[u] = (j < cnt) ? av : -INFINITY;
+        } else {
+          a[u] = av;
+        }
       };
       float zcur[NSL], znext[NSL];
       {
@@ -234,6 +251,7 @@ __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qb
 #pragma unroll
         for (int k = 0; k < NSL; ++k) zcur[k] = zr[k];
       }
+      float mn_prev = 0.f;
 #pragma unroll
       for (int u = 0; u < 32; ++u) {
         // the first use waits for this sample's coordinates; only then is the
@@ -258,19 +276,14 @@ __device__ __forceinline__ void sweep_pairs_block(const SweepArgs& A, int64_t qb
           const float y1 = fmaf(sg, zcur[2 * k + 1], us[2 * k + 1]);
           r2[k] = fmaf(y0, y0, y1 * y1);
         }
-        const float ell = __builtin_amdgcn_sqrtf(min_tree<MP>(r2)) - A.dp.r;
-        const float av = fmaf(-cl, ell, a0 - a[u]);
-        if constexpr (decltype(masked)::value) {
-          const int j = g0 + 8 * ((u & 15) / 4) + 4 * (u / 16) + (u & 3);
-          a[u] = (j < cnt) ? av : -INFINITY;
-        } else {
-          a[u] = av;
-        }
+        if (u > 0) finish(u - 1, mn_prev);
+        mn_prev = min_tree<MP>(r2);
         if (u + 1 < 32) {
 #pragma unroll
           for (int k = 0; k < NSL; ++k) zcur[k] = znext[k];
         }
       }
+      finish(31, mn_prev);
       float mb = a[0];
 #pragma unroll
       for (int u = 1; u < 32; ++u) mb = fmaxf(mb, a[u]);

@@ -99,11 +99,18 @@ def test_forward_matches_oracle(ctx, n, width, depth):
     sur.close()
 
 
-# B = 4,096 at width 256 takes the 64-row GEMM tiles (and 16 weight-gradient
-# splits with their bias sums); the smaller batches take the 32-row tiles.
-@pytest.mark.parametrize("n,width,depth,B", [(8, 64, 2, 256), (45, 256, 4, 256), (45, 256, 4, 4096)])
-def test_loss_and_gradients_match_oracle(ctx, n, width, depth, B):
+# Both training paths: the fused step (rows kernel + weight-gradient tiles;
+# batches of 256 .. 4,096) and the layer-by-layer GEMMs (HJG_MLP_FUSED=0, and
+# any batch the fused kernels are not built for, such as 320): B = 4,096 at
+# width 256 takes the 64-row GEMM tiles (and 16 weight-gradient splits with
+# their bias sums), the smaller batches the 32-row tiles.
+@pytest.mark.parametrize("path", ["fused", "layers"])
+@pytest.mark.parametrize("n,width,depth,B", [(8, 64, 2, 256), (45, 256, 4, 256), (45, 256, 4, 4096),
+                                             (9, 128, 3, 320)])
+def test_loss_and_gradients_match_oracle(ctx, monkeypatch, path, n, width, depth, B):
     from paper_2605_18566_amd import Surrogate
+    if path == "layers":
+        monkeypatch.setenv("HJG_MLP_FUSED", "0")
     sizes, layers, norm = random_net(n, width, depth, 3)
     sur = Surrogate(ctx, n, width, depth)
     sur.set_params(flat_from_layers(layers), norm)
