@@ -159,14 +159,20 @@ struct Best {
   }
 };
 
+// Candidates s in [a, e): four points requested together, then offered in
+// index order (the kept set does not depend on the order of the offers).
 template <int K>
 __device__ __forceinline__ void scan_range(Best<K>& b, const float4* sorted, int a, int e, int me, float x, float y,
                                            float z) {
-  for (int s = a; s < e; ++s) {
-    const float4 q = sorted[s];
-    const int j = __float_as_int(q.w);
-    if (j == me) continue;
-    b.offer(dist2_rounded(q.x - x, q.y - y, q.z - z), j, q);
+  for (int s = a; s < e; s += 4) {
+    float4 q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = sorted[min(s + u, e - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = __float_as_int(q[u].w);
+      if (s + u < e && j != me) b.offer(dist2_rounded(q[u].x - x, q[u].y - y, q[u].z - z), j, q[u]);
+    }
   }
 }
 
@@ -183,7 +189,42 @@ __global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, con
   for (int d = 0; d < 3; ++d) c[d] = cell_coord(xs[d], gg.lo[d], gg.inv_h, gg.g[d]);
   Best<K> b;
   b.init();
-  for (int r = 0;; ++r) {
+  // true once every point outside the cells within r (Chebyshev distance in
+  // cells) is farther than the k-th distance kept
+  auto done = [&](int r) {
+    float gap = INFINITY;
+    bool covered = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float slack = 1e-5f * (fabsf(gg.lo[d]) + (float)gg.g[d] * gg.h + fabsf(xs[d]));
+      if (c[d] - r > 0) {
+        covered = false;
+        gap = fminf(gap, xs[d] - (gg.lo[d] + (float)(c[d] - r) * gg.h) - slack);
+      }
+      if (c[d] + r < gg.g[d] - 1) {
+        covered = false;
+        gap = fminf(gap, gg.lo[d] + (float)(c[d] + r + 1) * gg.h - xs[d] - slack);
+      }
+    }
+    return covered || (gap > 0.f && b.d[K - 1] < gap * gap);
+  };
+  // cells within 1: the 3 x 3 rows of the block, each one contiguous range of
+  // the cell-ordered points; all 18 range bounds are requested together
+  {
+    int ra[9], re[9];
+    const int x0 = max(c[0] - 1, 0), x1 = min(c[0] + 1, gg.g[0] - 1);
+#pragma unroll
+    for (int w = 0; w < 9; ++w) {
+      const int z = c[2] + w / 3 - 1, y = c[1] + w % 3 - 1;
+      const bool in = z >= 0 && z < gg.g[2] && y >= 0 && y < gg.g[1];
+      const int row = in ? (z * gg.g[1] + y) * gg.g[0] : 0;
+      ra[w] = in ? start[row + x0] : 0;
+      re[w] = in ? start[row + x1 + 1] : 0;
+    }
+#pragma unroll
+    for (int w = 0; w < 9; ++w) scan_range<K>(b, sorted, ra[w], re[w], me, xs[0], xs[1], xs[2]);
+  }
+  for (int r = 2; !done(r - 1); ++r) {
     const int z0 = max(c[2] - r, 0), z1 = min(c[2] + r, gg.g[2] - 1);
     const int y0 = max(c[1] - r, 0), y1 = min(c[1] + r, gg.g[1] - 1);
     const int x0 = max(c[0] - r, 0), x1 = min(c[0] + r, gg.g[0] - 1);
@@ -199,23 +240,6 @@ __global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, con
         }
       }
     }
-    // nearest point any cell outside the scanned block can hold
-    float gap = INFINITY;
-    bool covered = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float slack = 1e-5f * (fabsf(gg.lo[d]) + (float)gg.g[d] * gg.h + fabsf(xs[d]));
-      if (c[d] - r > 0) {
-        covered = false;
-        gap = fminf(gap, xs[d] - (gg.lo[d] + (float)(c[d] - r) * gg.h) - slack);
-      }
-      if (c[d] + r < gg.g[d] - 1) {
-        covered = false;
-        gap = fminf(gap, gg.lo[d] + (float)(c[d] + r + 1) * gg.h - xs[d] - slack);
-      }
-    }
-    if (covered) break;
-    if (gap > 0.f && b.d[K - 1] < gap * gap) break;
   }
 #pragma unroll
   for (int s = 0; s < K; ++s) {
