@@ -163,6 +163,9 @@ __global__ __launch_bounds__(64 * NW) void fused_rows_kernel(FusedRowsArgs a) {
       constexpr int NN = FN ? (LN == D ? OUT : W) : W;
       PhaseW<KN, NN, NW> wn;
       load_phase<KN, NN, NW>(a.ph[PN].W, wave, lane, wn);
+      // keep the requests ahead of this phase's products (the scheduler
+      // would otherwise sink them into the freed registers of this phase)
+      __builtin_amdgcn_sched_barrier(0);
       run(ph, wcur);
       self(std::integral_constant<int, PN>{}, wn, self);
     } else {
@@ -187,14 +190,14 @@ __global__ __launch_bounds__(64 * NW) void fused_rows_kernel(FusedRowsArgs a) {
 // Operand lanes of v_mfma_f32_32x32x16_bf16: A[i = l%32][k = 8(l/32)..+7],
 // B[k = 8(l/32)..+7][j = l%32]; result lane l holds rows 8(v/4) + 4(l/32) + v%4
 // of column l%32.  The NWV waves split the batch (NST k-steps of 16 each); the
-// loop is unrolled at compile time, the operands of the next 16 k-steps
-// requested before the products of the current 16.
+// loop is unrolled at compile time, the operands of the next 8 k-steps
+// requested before the products of the current 8.
 // Consecutive blocks go to different XCDs (round robin), so tiles are
 // assigned in contiguous ranges per XCD: the tiles of one range share their
 // row blocks of dz^T in that XCD's L2.
 template <int NST, int NWV>
 __global__ __launch_bounds__(64 * NWV) void fused_weights_kernel(FusedWeightsArgs a) {
-  constexpr int CH = NST < 16 ? NST : 16;   // k-steps per chunk
+  constexpr int CH = NST < 8 ? NST : 8;     // k-steps per chunk
   constexpr int NCH = NST / CH;
   static_assert(NST % CH == 0, "k-steps per wave");
   __shared__ float part[NWV][16][64];
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(64 * NWV) void fused_weights_kernel(FusedWeightsArg
         bv[1 - cur][i] = *bptr((c + 1) * CH + i);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);   // the next chunk's requests stay ahead of these products
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][i], bv[cur][i], acc, 0, 0, 0);
