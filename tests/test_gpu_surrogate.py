@@ -332,6 +332,40 @@ def test_recorded_training_steps_match_direct_launches(ctx, monkeypatch):
     np.testing.assert_array_equal(hists[0], hists[1])
 
 
+def test_fused_and_layer_training_paths_agree(ctx, monkeypatch):
+    # the fused step (learning rate and bias corrections from the host's
+    # per-epoch table, the epoch's permuted copy of the training set) and the
+    # layer-by-layer step (the same quantities from device counters, a gather
+    # per step) are the same AdamW training: from the same initial network
+    # the parameters after 3 epochs agree to the rounding of the bfloat16
+    # operands (the two sum the products in different orders)
+    from paper_2605_18566_amd import Surrogate, TrainConfig
+    n, M = 9, 8192
+    rng = np.random.default_rng(21)
+    x = rng.uniform(-2, 2, (n, M)).astype(np.float32)
+    t = rng.uniform(0.2, 1.0, M).astype(np.float32)
+    v = (np.sin(x[0]) * t).astype(np.float32)
+    g = np.zeros((n, M), np.float32)
+    g[0] = np.cos(x[0]) * t
+    cfg = TrainConfig(epochs=3, batch=1024, lr=3e-3, lr_min=1e-4, weight_decay=1e-4, seed=8)
+    params, hists = [], []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HJG_MLP_FUSED", mode)
+        sur = Surrogate(ctx, n, 128, 3, seed=4)
+        p0 = sur.get_params()[0].copy()
+        hists.append(sur.train(to_dev(x), to_dev(t), to_dev(v), to_dev(g), cfg))
+        params.append((p0, sur.get_params()[0]))
+        sur.close()
+    (a0, a1), (b0, b1) = params
+    np.testing.assert_array_equal(a0, b0)
+    step_a, step_b = a1 - a0, b1 - b0
+    rel = np.linalg.norm(step_a - step_b) / np.linalg.norm(step_a)
+    print(f"parameter change: |fused| {np.linalg.norm(step_a):.4g}, relative difference {rel:.3e}; "
+          f"loss fused {hists[0].round(5).tolist()}, layers {hists[1].round(5).tolist()}", flush=True)
+    assert rel < 0.05
+    np.testing.assert_allclose(hists[0], hists[1], rtol=0.02)
+
+
 def test_save_load_round_trip_and_bad_files(ctx, tmp_path):
     from paper_2605_18566_amd import Surrogate, _lib
     sizes, layers, norm = random_net(5, 64, 2, 21)
