@@ -224,12 +224,28 @@ hipError_t launch_tube_lse(const TubeLseArgs& a, hipStream_t s);
 
 // Item index a block of a persistent batched launch serves next: taken from
 // the work queue by one thread and shared through LDS; count or more = done.
+// The batched launches' problem records and work items are written by the
+// host before the launch and only read while it runs.  Reading them through
+// the constant address space lets the compiler use scalar loads for them
+// (the item index is uniform), and take a field again from the scalar cache
+// where it does not keep it in a register, instead of a vector load and a
+// wait inside the pair loop.
+__device__ __forceinline__ int4 work_item(const int4* items, int b) {
+  return *(const int4*)((const __attribute__((address_space(4))) int4*)items + b);
+}
+
+__device__ __forceinline__ const SweepArgs& problem_args(const SweepArgs* probs, int p) {
+  return *(const SweepArgs*)((const __attribute__((address_space(4))) SweepArgs*)probs + p);
+}
+
 __device__ __forceinline__ int next_item(int* counter, int* slot) {
   if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
   __syncthreads();
   const int b = *slot;
   __syncthreads();
-  return b;
+  // every lane read the same value: make it a scalar, so that the item's
+  // record and its problem's arguments are read through the scalar cache
+  return __builtin_amdgcn_readfirstlane(b);
 }
 
 // Uniform hash grid over agent positions: cell (x, y, z) covers

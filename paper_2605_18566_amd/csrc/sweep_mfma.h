@@ -334,8 +334,8 @@ __global__ __launch_bounds__(256) void sweep_mfma_batched_kernel(const SweepArgs
   __shared__ int slot;
   for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
        b = counter ? next_item(counter, &slot) : count) {
-    const int4 it = items[b];
-    const SweepArgs& A = probs[it.x];
+    const int4 it = work_item(items, b);
+    const SweepArgs& A = problem_args(probs, it.x);
     if (A.done && *A.done) continue;
     sweep_mfma_block<DATUM, NM, MP>(A, it.y, it.z);
   }

@@ -395,8 +395,8 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   __shared__ int slot;
   for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
        b = counter ? next_item(counter, &slot) : count) {
-    const int4 it = items[b];
-    const SweepArgs& A = probs[it.x];
+    const int4 it = work_item(items, b);
+    const SweepArgs& A = problem_args(probs, it.x);
     if (A.done && *A.done) continue;
     sweep_pairs_block<NM, MP>(A, it.y, it.z);
   }
