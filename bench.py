@@ -310,6 +310,36 @@ def batched_study(ctx, stream, P: int = 256):
             "one_call_per_problem_includes": "per-call table generation and graph recording (16-graph cache)"}
 
 
+def batched_headline(steps: int):
+    """The headline problem alone through the batched path (P = 1) and through
+    the single-problem path, `steps` timed calls each after one recording call:
+    for comparing the two pair-loop kernels on the same work in one trace."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import Context, ProblemSpec, picard_sweep, picard_sweep_batched
+    w = workloads.C5
+    x = torch.from_numpy(np.ascontiguousarray(workloads.queries(w, trial=1).T)).to(torch.device("cuda:0"))
+    spec = ProblemSpec(**w.problem_fields())
+    ctx = Context(0)
+    calls = {"single": lambda: picard_sweep(ctx, spec, x, w.t, w.N, w.K, host_outputs=False),
+             "batched": lambda: picard_sweep_batched(ctx, [spec], [x], [w.N], [w.K], [w.t], host_outputs=False)}
+    secs = {}
+    for name, call in calls.items():
+        call()
+        torch.cuda.synchronize()
+        secs[name] = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            secs[name].append(time.perf_counter() - t0)
+    ctx.close()
+    return {"workload": f"{w.name} alone, batched path (P = 1) and single-problem path",
+            "seconds": secs, "batch_split": os.environ.get("HJG_BATCH_SPLIT", "default")}
+
+
 def batched_only(steps: int):
     """The uneven batch alone: one recording call, then `steps` timed calls of
     the batched sweep (no other work), for per-kernel profiles."""
@@ -940,6 +970,9 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the uneven batch (one batched call, --steps times after one recording call) "
                          "and print its wall time; for kernel profiles of the batched launches")
+    ap.add_argument("--batched-headline", action="store_true",
+                    help="run only the headline problem through the batched path (P = 1) and the "
+                         "single-problem path, --steps calls each; for comparing the two kernels")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -980,6 +1013,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps(batched_only(args.steps)))
+        return
+    if args.batched_headline:
+        print(json.dumps(batched_headline(args.steps)))
         return
 
     w = workloads.C5
