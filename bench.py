@@ -983,7 +983,11 @@ def main():
         from paper_2605_18566_amd import probe_valu_rate
         rows = []
         forms = {0: "fma acc*s+s (scalar operand)", 1: "fmac acc+=a*b", 2: "mul acc*=a", 3: "fma acc*a+b",
-                 4: "fmac acc+=s*a (scalar operand)", 5: "add acc+=s (scalar operand)", 6: "min3 (acc, a, b)"}
+                 4: "fmac acc+=s*a (scalar operand)", 5: "add acc+=s (scalar operand)", 6: "min3 (acc, a, b)",
+                 7: "forms 0 and 1 on alternate chains",
+                 8: "asm S F S F, independent", 9: "asm S F S F, F reads the S before it",
+                 10: "asm S F S F, F reads the S two before it",
+                 11: "fmac acc+=a*b at 256 VGPRs", 12: "asm S F S F, F reads the S two before it, at 256 VGPRs"}
         for form, what in forms.items():
             for wps in (1, 2, 4, 8):
                 r, ghz = probe_valu_rate(wps, form=form)

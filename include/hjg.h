@@ -376,8 +376,13 @@ int hjg_tuning_load(hjg_ctx* ctx, const char* path);
  * chains for iters x 8 steps.  form 0: acc = acc * s + s with scalar s
  * (three-operand FMA); 1: acc += a * b with per-lane a, b (accumulating FMA);
  * 2: acc *= a; 3: acc = acc * a + b (three-operand FMA, per-lane operands);
- * 4: acc += s * a; 5: acc += s; 6: acc = min(acc, a, b).  Writes the wave-level VALU instructions per compute-unit
- * clock (the chip's float32 vector peak, 157.3 TFLOP/s, is 2.0 per clock)
+ * 4: acc += s * a; 5: acc += s; 6: acc = min(acc, a, b); 7: forms 0 and 1
+ * on alternate chains; 8-10: fixed inline-assembly sequences alternating
+ * a scalar-operand FMA (S) and a vector-register accumulating FMA (F):
+ * 8 independent, 9 each F reading the S just before it, 10 each F reading
+ * the S two before it; 11 and 12: forms 1 and 10 with 256 vector registers
+ * allocated (at most two waves per SIMD).  Writes the wave-level VALU instructions per
+ * compute-unit clock (the chip's float32 vector peak, 157.3 TFLOP/s, is 2.0 per clock)
  * and the shader clock in GHz measured by the waves (shader-clock ticks
  * against the 100 MHz real-time counter).  Allocates a small workspace,
  * synchronises the stream.  Errors: HJG_EINVAL (arguments), HJG_ENOMEM,

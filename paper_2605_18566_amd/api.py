@@ -329,7 +329,8 @@ def autotune_sweep(ctx: Context, spec: ProblemSpec, x: torch.Tensor, t: float, N
 def probe_valu_rate(waves_per_simd: int, iters: int = 20000, form: int = 0, stream=None):
     """Issue rate of independent unpacked float32 operations at waves_per_simd
     resident waves per SIMD (form 0: FMA with a scalar operand, 1: accumulating
-    FMA, 2: multiply): (wave-level VALU instructions per compute-unit clock,
+    FMA, 2: multiply, ... 7: forms 0 and 1 on alternate chains, 8-10: fixed
+    sequences with different dependences; include/hjg.h lists all thirteen): (wave-level VALU instructions per compute-unit clock,
     shader clock in GHz).  A measurement helper for the vector-ALU roofline."""
     r, g = C.c_double(0.0), C.c_double(0.0)
     check(_lib.lib().hjg_probe_valu_rate(int(waves_per_simd), int(iters), int(form), C.byref(r), C.byref(g),

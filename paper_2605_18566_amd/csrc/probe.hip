@@ -28,7 +28,21 @@ int fail(int code, const std::string& msg) { return hjg_internal_fail(code, msg.
 // FORM 3: acc = acc * a + b with a, b per lane (three-operand FMA, vector operands);
 // FORM 4: acc = acc + s * a (accumulating FMA with a scalar operand);
 // FORM 5: acc = acc + s (add with a scalar operand);
-// FORM 6: acc = min(acc, a, b) (three-input minimum).
+// FORM 6: acc = min(acc, a, b) (three-input minimum);
+// FORM 7: forms 0 and 1 on alternate chains (half the instructions read a
+// scalar operand, as in the pair loop's offsets and squares).
+// FORMS 8-10 fix the order and registers in inline assembly (vector-ALU
+// instructions only), four instructions per step alternating a three-operand
+// FMA with a scalar operand (S) and an accumulating FMA of vector registers
+// (F), to separate the effect of dependences:
+// FORM 8: S F S F, all independent;
+// FORM 9: each F reads the result of the S just before it;
+// FORM 10: each F reads the result of the S two before it, and the next S
+// overwrites the register that F read (the pair loop's offset-square
+// pattern).
+// FORMS 11 and 12: forms 1 and 10 with the kernel's register allocation
+// raised to 256 vector registers (at most two waves per SIMD), as in the
+// pair loop.
 template <int FORM>
 __global__ __launch_bounds__(256) void valu_probe_kernel(int32_t iters, float mul, float add, float* sink,
                                                          unsigned long long* ticks) {
@@ -37,6 +51,7 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(int32_t iters, float mu
 #pragma unroll
   for (int k = 0; k < kChains; ++k) acc[k] = 1.0f + 1e-3f * (float)(lane + k);
   const float va = mul + 1e-9f * (float)lane, vb = add * (1.0f + 1e-9f * (float)lane);
+  if constexpr (FORM >= 11) asm volatile("; holds the top register" ::: "v255");
   const unsigned long long c0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
@@ -44,12 +59,30 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(int32_t iters, float mu
 #pragma unroll
       for (int k = 0; k < kChains; ++k) {
         if constexpr (FORM == 0) acc[k] = fmaf(acc[k], mul, add);
-        else if constexpr (FORM == 1) acc[k] = fmaf(va, vb, acc[k]);
+        else if constexpr (FORM == 1 || FORM == 11) acc[k] = fmaf(va, vb, acc[k]);
         else if constexpr (FORM == 2) acc[k] = acc[k] * va;
         else if constexpr (FORM == 3) acc[k] = fmaf(acc[k], va, vb);
         else if constexpr (FORM == 4) acc[k] = fmaf(mul, va, acc[k]);
         else if constexpr (FORM == 5) acc[k] = acc[k] + add;
-        else acc[k] = fminf(fminf(acc[k], va), vb);
+        else if constexpr (FORM == 6) acc[k] = fminf(fminf(acc[k], va), vb);
+        else if constexpr (FORM == 7) acc[k] = (k & 1) ? fmaf(va, vb, acc[k]) : fmaf(acc[k], mul, add);
+        else if (k % 4 == 0) {
+          if constexpr (FORM == 8)
+            asm volatile("v_fma_f32 %0, %6, %4, %5\n\tv_fmac_f32 %1, %4, %5\n\t"
+                         "v_fma_f32 %2, %6, %4, %5\n\tv_fmac_f32 %3, %4, %5"
+                         : "+v"(acc[k]), "+v"(acc[k + 1]), "+v"(acc[k + 2]), "+v"(acc[k + 3])
+                         : "v"(va), "v"(vb), "s"(mul));
+          else if constexpr (FORM == 9)
+            asm volatile("v_fma_f32 %0, %6, %4, %5\n\tv_fmac_f32 %1, %0, %0\n\t"
+                         "v_fma_f32 %2, %6, %4, %5\n\tv_fmac_f32 %3, %2, %2"
+                         : "+v"(acc[k]), "+v"(acc[k + 1]), "+v"(acc[k + 2]), "+v"(acc[k + 3])
+                         : "v"(va), "v"(vb), "s"(mul));
+          else if constexpr (FORM == 10 || FORM == 12)
+            asm volatile("v_fma_f32 %0, %6, %4, %5\n\tv_fmac_f32 %1, %2, %2\n\t"
+                         "v_fma_f32 %2, %6, %4, %5\n\tv_fmac_f32 %3, %0, %0"
+                         : "+v"(acc[k]), "+v"(acc[k + 1]), "+v"(acc[k + 2]), "+v"(acc[k + 3])
+                         : "v"(va), "v"(vb), "s"(mul));
+        }
       }
   }
   const unsigned long long c1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
@@ -71,7 +104,7 @@ int hjg_probe_valu_rate(int32_t waves_per_simd, int32_t iters, int32_t form, dou
   if (!instr_per_cu_clock || !clock_ghz) return fail(HJG_EINVAL, "NULL argument");
   if (waves_per_simd < 1 || waves_per_simd > 8) return fail(HJG_EINVAL, "waves_per_simd must be in [1, 8]");
   if (iters < 1 || iters > (1 << 24)) return fail(HJG_EINVAL, "iters must be in [1, 2^24]");
-  if (form < 0 || form > 6) return fail(HJG_EINVAL, "form must be in [0, 6]");
+  if (form < 0 || form > 12) return fail(HJG_EINVAL, "form must be in [0, 12]");
   hipStream_t st = (hipStream_t)hip_stream;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -101,7 +134,13 @@ int hjg_probe_valu_rate(int32_t waves_per_simd, int32_t iters, int32_t form, dou
       case 3: valu_probe_kernel<3><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
       case 4: valu_probe_kernel<4><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
       case 5: valu_probe_kernel<5><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
-      default: valu_probe_kernel<6><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 6: valu_probe_kernel<6><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 7: valu_probe_kernel<7><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 8: valu_probe_kernel<8><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 9: valu_probe_kernel<9><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 10: valu_probe_kernel<10><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      case 11: valu_probe_kernel<11><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
+      default: valu_probe_kernel<12><<<blocks, 256, 0, st>>>(it, 0.9999f, 1e-4f, sink, ticks); break;
     }
   };
   launch(std::max(1, iters / 16));

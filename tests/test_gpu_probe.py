@@ -24,4 +24,4 @@ def test_valu_probe_rejects_bad_arguments():
     with pytest.raises(_lib.HJGError):
         probe_valu_rate(9)
     with pytest.raises(_lib.HJGError):
-        probe_valu_rate(1, form=7)
+        probe_valu_rate(1, form=13)
