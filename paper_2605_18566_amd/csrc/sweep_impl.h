@@ -243,11 +243,13 @@ __device__ __forceinline__ void write_partials(const SweepArgs& A, const LseAcc<
 }
 
 // ------------------------------------------------------------ common table (CRN)
-// One block of the pair loop: queries qblock*256 .. +255, sample split `split`.
+// One block of the pair loop: queries qblock*QB .. +QB-1 (QB =
+// kQueriesPerBlockValu, one per thread), sample split `split`.
 template <int DATUM, int NM, int MP, bool BF16>
 __device__ __forceinline__ void sweep_crn_block(const SweepArgs& A, int64_t qblock, int split) {
+  constexpr int QB = kQueriesPerBlockValu;
   __shared__ float zs[NM][kBlk];
-  const int64_t q = qblock * kThreads + threadIdx.x;
+  const int64_t q = qblock * QB + threadIdx.x;
   const bool active = q < A.Q;
   const int64_t qs = active ? q : A.Q - 1;   // a valid state to read for idle lanes
   const int i_begin = split * A.ns;
@@ -260,7 +262,7 @@ __device__ __forceinline__ void sweep_crn_block(const SweepArgs& A, int64_t qblo
 
   for (int i0 = i_begin; i0 < i_end; i0 += kBlk) {
     const int cnt = min(kBlk, i_end - i0);
-    for (int e = threadIdx.x; e < NM * kBlk; e += kThreads) {
+    for (int e = threadIdx.x; e < NM * kBlk; e += QB) {
       const int d = e / kBlk, j = e % kBlk;
       float z = 0.f;
       if (d < A.n && j < cnt) {
@@ -301,7 +303,7 @@ __device__ __forceinline__ void sweep_crn_block(const SweepArgs& A, int64_t qblo
 }
 
 template <int DATUM, int NM, int MP, bool BF16>
-__global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
+__global__ __launch_bounds__(kQueriesPerBlockValu) void sweep_crn_kernel(SweepArgs A) {
   if (A.done && *A.done) return;
   sweep_crn_block<DATUM, NM, MP, BF16>(A, blockIdx.x, blockIdx.y);
 }
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void sweep_crn_kernel(SweepArgs A) {
 // Many problems in one launch: block b serves work item items[b] =
 // (problem, query block, sample split) with that problem's arguments.
 template <int DATUM, int NM, int MP, bool BF16>
-__global__ __launch_bounds__(kThreads) void sweep_crn_batched_kernel(const SweepArgs* probs, const int4* items,
+__global__ __launch_bounds__(kQueriesPerBlockValu) void sweep_crn_batched_kernel(const SweepArgs* probs, const int4* items,
                                                                      int count, int* counter) {
   __shared__ int slot;
   for (int b = counter ? next_item(counter, &slot) : (int)blockIdx.x; b < count;
@@ -422,11 +424,11 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
   if (b) {
     if (fresh) return hipErrorInvalidValue;
     if (bf16) {
-      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, true>, kThreads, b);
-      sweep_crn_batched_kernel<DATUM, NM, MP, true><<<g, kThreads, 0, s>>>(b->probs, b->items, b->count, b->counter);
+      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, true>, kQueriesPerBlockValu, b);
+      sweep_crn_batched_kernel<DATUM, NM, MP, true><<<g, kQueriesPerBlockValu, 0, s>>>(b->probs, b->items, b->count, b->counter);
     } else {
-      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, false>, kThreads, b);
-      sweep_crn_batched_kernel<DATUM, NM, MP, false><<<g, kThreads, 0, s>>>(b->probs, b->items, b->count, b->counter);
+      const unsigned g = batch_grid(sweep_crn_batched_kernel<DATUM, NM, MP, false>, kQueriesPerBlockValu, b);
+      sweep_crn_batched_kernel<DATUM, NM, MP, false><<<g, kQueriesPerBlockValu, 0, s>>>(b->probs, b->items, b->count, b->counter);
     }
     return hipGetLastError();
   }
@@ -439,8 +441,10 @@ hipError_t launch_sweep_dn(const SweepArgs& a, int fresh, int bf16, hipStream_t 
       return hipErrorInvalidValue;
     }
   } else {
-    if (bf16) sweep_crn_kernel<DATUM, NM, MP, true><<<grid, kThreads, 0, s>>>(a);
-    else sweep_crn_kernel<DATUM, NM, MP, false><<<grid, kThreads, 0, s>>>(a);
+    constexpr int QB = kQueriesPerBlockValu;
+    const dim3 gridc((unsigned)((a.Q + QB - 1) / QB), (unsigned)a.splits);
+    if (bf16) sweep_crn_kernel<DATUM, NM, MP, true><<<gridc, QB, 0, s>>>(a);
+    else sweep_crn_kernel<DATUM, NM, MP, false><<<gridc, QB, 0, s>>>(a);
   }
   return hipGetLastError();
 }
