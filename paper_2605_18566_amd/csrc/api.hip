@@ -1518,7 +1518,7 @@ extern "C" int hjg_knn_grid(hjg_ctx* ctx, int64_t M, const float* pos, const flo
   if (host) return fail(HJG_ENONFINITE, "non-finite agent position");
   HJG_HIP(launch_grid_build(pos, M, gg, (int*)ctx->g_cell.p, (int*)ctx->g_rank.p, (int*)ctx->g_start.p,
                             (int*)ctx->g_bsum.p, (float4*)ctx->g_sorted.p, s));
-  HJG_HIP(launch_knn((const float4*)ctx->g_sorted.p, (const int*)ctx->g_start.p, M, gg, k, idx, nbr_pos, s));
+  HJG_HIP(launch_knn((const float4*)ctx->g_sorted.p, (const int*)ctx->g_start.p, pos, M, gg, k, idx, nbr_pos, s));
   return HJG_OK;
 }
 

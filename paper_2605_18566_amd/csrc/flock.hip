@@ -121,41 +121,37 @@ __global__ __launch_bounds__(kThreads) void grid_scatter_kernel(const float* pos
   sorted[start[cell[i]] + rank[i]] = make_float4(pos[i], pos[M + i], pos[2 * M + i], __int_as_float((int)i));
 }
 
-__device__ __forceinline__ bool before(float da, int ia, float db, int ib) {
-  return da < db || (da == db && ia < ib);
+// The k nearest so far, ascending in the strict order (distance, index),
+// each kept as one 64-bit key: the squared distance's bits (a non-negative
+// float orders like its bit pattern) above the agent index, so the order is
+// one unsigned comparison.  Positions are read once at the end.
+__device__ __forceinline__ uint64_t knn_key(float d2, int j) {
+  return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)j;
 }
+
+constexpr uint64_t kNoKey = ((uint64_t)0x7F800000u << 32) | 0x7FFFFFFFu;   // (INFINITY, 0x7FFFFFFF)
 
 template <int K>
 struct Best {
-  float d[K];
-  int i[K];
-  float p[K][3];
+  uint64_t key[K];
 
   __device__ void init() {
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-      d[s] = INFINITY;
-      i[s] = 0x7FFFFFFF;
-      p[s][0] = p[s][1] = p[s][2] = 0.f;
-    }
+    for (int s = 0; s < K; ++s) key[s] = kNoKey;
   }
-  // insert (d2, j) at position q, q in registers via unrolled compare-swap
-  __device__ void offer(float d2, int j, const float4& q) {
-    if (!before(d2, j, d[K - 1], i[K - 1])) return;
-    d[K - 1] = d2;
-    i[K - 1] = j;
-    p[K - 1][0] = q.x;
-    p[K - 1][1] = q.y;
-    p[K - 1][2] = q.z;
+  __device__ float d(int s) const { return __uint_as_float((uint32_t)(key[s] >> 32)); }
+  __device__ int i(int s) const { return (int)(uint32_t)key[s]; }
+  // insert a key without a branch: every comparison with the kept keys is
+  // independent, and entry s takes its left neighbour, the new key or itself
+  // (a key that is not below the last changes nothing; kNoKey stands for no
+  // candidate)
+  __device__ void offer(uint64_t k) {
+    bool lt[K];
 #pragma unroll
-    for (int s = K - 1; s > 0; --s) {
-      if (before(d[s], i[s], d[s - 1], i[s - 1])) {
-        float td = d[s]; d[s] = d[s - 1]; d[s - 1] = td;
-        int ti = i[s]; i[s] = i[s - 1]; i[s - 1] = ti;
+    for (int s = 0; s < K; ++s) lt[s] = k < key[s];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) { float tp = p[s][e]; p[s][e] = p[s - 1][e]; p[s - 1][e] = tp; }
-      }
-    }
+    for (int s = K - 1; s > 0; --s) key[s] = lt[s - 1] ? key[s - 1] : (lt[s] ? k : key[s]);
+    key[0] = lt[0] ? k : key[0];
   }
 };
 
@@ -171,14 +167,15 @@ __device__ __forceinline__ void scan_range(Best<K>& b, const float4* sorted, int
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = __float_as_int(q[u].w);
-      if (s + u < e && j != me) b.offer(dist2_rounded(q[u].x - x, q[u].y - y, q[u].z - z), j, q[u]);
+      const bool ok = s + u < e && j != me;
+      b.offer(ok ? knn_key(dist2_rounded(q[u].x - x, q[u].y - y, q[u].z - z), j) : kNoKey);
     }
   }
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, const int* start, int64_t M, GridGeom gg,
-                                                       int32_t* idx, float* nbr) {
+__global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, const int* start, const float* pos,
+                                                       int64_t M, GridGeom gg, int32_t* idx, float* nbr) {
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= M) return;
   const float4 self = sorted[t];
@@ -206,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, con
         gap = fminf(gap, gg.lo[d] + (float)(c[d] + r + 1) * gg.h - xs[d] - slack);
       }
     }
-    return covered || (gap > 0.f && b.d[K - 1] < gap * gap);
+    return covered || (gap > 0.f && b.d(K - 1) < gap * gap);
   };
   // cells within 1: the 3 x 3 rows of the block, each one contiguous range of
   // the cell-ordered points; all 18 range bounds are requested together
@@ -243,10 +240,13 @@ __global__ __launch_bounds__(kThreads) void knn_kernel(const float4* sorted, con
   }
 #pragma unroll
   for (int s = 0; s < K; ++s) {
-    if (idx) idx[(int64_t)s * M + me] = b.i[s];
+    const int j = b.i(s);
+    if (idx) idx[(int64_t)s * M + me] = j;
     if (nbr) {
+      // an empty slot (fewer than k other agents) keeps the origin
+      const bool real = j != 0x7FFFFFFF;
 #pragma unroll
-      for (int e = 0; e < 3; ++e) nbr[(int64_t)(3 * s + e) * M + me] = b.p[s][e];
+      for (int e = 0; e < 3; ++e) nbr[(int64_t)(3 * s + e) * M + me] = real ? pos[(int64_t)e * M + j] : 0.f;
     }
   }
 }
@@ -269,18 +269,18 @@ hipError_t launch_grid_build(const float* pos, int64_t M, const GridGeom& gg, in
   return hipGetLastError();
 }
 
-hipError_t launch_knn(const float4* sorted, const int* start, int64_t M, const GridGeom& gg, int k, int32_t* idx,
-                      float* nbr, hipStream_t s) {
+hipError_t launch_knn(const float4* sorted, const int* start, const float* pos, int64_t M, const GridGeom& gg, int k,
+                      int32_t* idx, float* nbr, hipStream_t s) {
   const int gm = (int)((M + kThreads - 1) / kThreads);
   switch (k) {
-    case 1: knn_kernel<1><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 2: knn_kernel<2><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 3: knn_kernel<3><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 4: knn_kernel<4><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 5: knn_kernel<5><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 6: knn_kernel<6><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    case 7: knn_kernel<7><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
-    default: knn_kernel<8><<<gm, kThreads, 0, s>>>(sorted, start, M, gg, idx, nbr); break;
+    case 1: knn_kernel<1><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 2: knn_kernel<2><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 3: knn_kernel<3><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 4: knn_kernel<4><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 5: knn_kernel<5><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 6: knn_kernel<6><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    case 7: knn_kernel<7><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
+    default: knn_kernel<8><<<gm, kThreads, 0, s>>>(sorted, start, pos, M, gg, idx, nbr); break;
   }
   return hipGetLastError();
 }

@@ -262,9 +262,10 @@ constexpr int64_t kMaxGridCells = int64_t(1) << 26;
 // (x, y, z, agent index bits) in cell order.
 hipError_t launch_grid_build(const float* pos, int64_t M, const GridGeom& gg, int* cell, int* rank, int* start,
                              int* bsum, float4* sorted, hipStream_t s);
-// k (1..8) nearest other agents: idx [k][M], nbr [k][3][M] (either may be null).
-hipError_t launch_knn(const float4* sorted, const int* start, int64_t M, const GridGeom& gg, int k, int32_t* idx,
-                      float* nbr, hipStream_t s);
+// k (1..8) nearest other agents: idx [k][M], nbr [k][3][M] (either may be
+// null); pos is the agents' positions [3][M] the grid was built from.
+hipError_t launch_knn(const float4* sorted, const int* start, const float* pos, int64_t M, const GridGeom& gg, int k,
+                      int32_t* idx, float* nbr, hipStream_t s);
 
 // Queries per block of the pair-loop kernels: vector ALU, generic matrix
 // core, stacked disc pairs on the matrix cores (one query per lane).
