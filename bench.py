@@ -340,6 +340,32 @@ def batched_headline(steps: int):
             "seconds": secs, "batch_split": os.environ.get("HJG_BATCH_SPLIT", "default")}
 
 
+def knn_only(steps: int):
+    """The 100,000-agent flock's 7-NN grid search alone, `steps` calls after
+    one untimed call: for kernel traces and counters of the search."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_18566_amd import Context, knn_grid
+    w = workloads.C4
+    st = workloads.flock_agents(w.Q, trial=0)
+    pos = torch.from_numpy(np.ascontiguousarray(st[:, :3].T)).to(torch.device("cuda:0"))
+    ext, k = workloads.FLOCK_EXTENT, int(w.datum_p[1])
+    ctx = Context(0)
+    idx, nbr = knn_grid(ctx, pos, (0, 0, 0), (ext,) * 3, workloads.FLOCK_CELL, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        knn_grid(ctx, pos, (0, 0, 0), (ext,) * 3, workloads.FLOCK_CELL, k, want_idx=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / max(steps, 1) * 1e3
+    i64 = idx.cpu().numpy().astype(np.int64)
+    ctx.close()
+    return {"workload": f"{w.name}: {w.Q} agents, {k}-NN grid search", "ms_per_call": ms,
+            "idx_sum": int(i64.sum()), "nbr_sum": float(nbr.double().sum())}
+
+
 def batched_only(steps: int):
     """The uneven batch alone: one recording call, then `steps` timed calls of
     the batched sweep (no other work), for per-kernel profiles."""
@@ -973,6 +999,8 @@ def main():
     ap.add_argument("--batched-headline", action="store_true",
                     help="run only the headline problem through the batched path (P = 1) and the "
                          "single-problem path, --steps calls each; for comparing the two kernels")
+    ap.add_argument("--knn-only", action="store_true",
+                    help="run only the flock's k-NN grid search, --steps calls; for kernel traces and counters")
     ap.add_argument("--cpu-queries-per-worker", type=int, default=96)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -1020,6 +1048,9 @@ def main():
         return
     if args.batched_headline:
         print(json.dumps(batched_headline(args.steps)))
+        return
+    if args.knn_only:
+        print(json.dumps(knn_only(args.steps)))
         return
 
     w = workloads.C5
