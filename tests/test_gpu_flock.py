@@ -73,6 +73,17 @@ def test_knn_duplicates_break_ties_by_index(ctx):
     check_against_oracle(pos, idx, nbr)
 
 
+def test_knn_lattice_equal_distances_break_ties_by_index(ctx):
+    # integer lattice: six neighbours at distance 1 and twelve at sqrt(2), so
+    # the seventh neighbour is a tie among twelve, settled by the lowest index
+    g = np.arange(8, dtype=np.float32)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    perm = np.random.default_rng(8).permutation(len(pos))      # indices not in lattice order
+    pos = np.ascontiguousarray(pos[perm])
+    idx, nbr = gpu_knn(ctx, pos, k=7, cell=1.0)
+    check_against_oracle(pos, idx, nbr)
+
+
 def test_knn_sparse_points_need_wide_shells(ctx):
     # 20 agents in a 100^3 box with cell 1: neighbours lie many cells away
     pos = np.random.default_rng(4).uniform(0, 100, (20, 3)).astype(np.float32)
